@@ -1,0 +1,165 @@
+"""ctypes binding of the FP64 CPU oracle (``qew_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: used by ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py``; the GPU library never imports it.
+
+Every function follows the paper (arXiv:1211.7275): Eq. (1) integrated by the
+explicit Euler method on a periodic chain (Sec. III B), pinning force from
+random values at integer u with a cubic spline (Sec. III B; RB force is minus
+the derivative of the potential, Sec. II), observables of Eqs. (3)-(5).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+RF = 0
+RB = 1
+
+_lib = None
+
+
+def lib():
+    """Load ``liboracle.so``, building it first if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    L = ctypes.CDLL(_build.LIB)
+    u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+    f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+    i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+    c_int, c_i64, c_u64, c_u32, c_d = (ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                       ctypes.c_uint32, ctypes.c_double)
+    L.qo_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.qo_philox_many.argtypes = [u32p, c_u64, u32p, c_i64]
+    L.qo_node.argtypes = [c_int, c_u64, c_u32, c_i64, c_i64]
+    L.qo_node.restype = c_d
+    L.qo_cr_value.argtypes = [f64p, c_d]
+    L.qo_cr_value.restype = c_d
+    L.qo_cr_slope.argtypes = [f64p, c_d]
+    L.qo_cr_slope.restype = c_d
+    L.qo_pinning.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d]
+    L.qo_pinning.restype = c_d
+    L.qo_potential.argtypes = [c_d, c_u64, c_u32, c_i64, c_d]
+    L.qo_potential.restype = c_d
+    L.qo_forces.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d, c_d, f64p, f64p]
+    L.qo_measure.argtypes = [c_i64, f64p, f64p, ctypes.POINTER(c_d), ctypes.POINTER(c_d),
+                             ctypes.POINTER(c_d)]
+    L.qo_euler.argtypes = [c_i64, c_d, f64p, f64p, f64p]
+    L.qo_run.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d, c_d, c_d, c_i64, c_i64,
+                         i64p, ctypes.c_int32, f64p, f64p, f64p, f64p]
+    L.qo_run.restype = c_int
+    L.qo_set_threads.argtypes = [c_int]
+    L.qo_get_threads.restype = c_int
+    _lib = L
+    return L
+
+
+def set_threads(n):
+    lib().qo_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().qo_get_threads())
+
+
+def philox(ctr, key):
+    """Philox4x32-10 of one counter (4 words) under one key (2 words)."""
+    out = np.zeros(4, np.uint32)
+    lib().qo_philox4x32_10(np.ascontiguousarray(ctr, np.uint32),
+                           np.ascontiguousarray(key, np.uint32), out)
+    return out
+
+
+def philox_many(ctr, seed):
+    ctr = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    out = np.zeros_like(ctr)
+    lib().qo_philox_many(ctr, int(seed), out, ctr.shape[0])
+    return out
+
+
+def node(kind, seed, did, j, n):
+    """Unscaled disorder value at integer u = n of column j."""
+    return lib().qo_node(int(kind), int(seed), int(did), int(j), int(n))
+
+
+def cr_value(p, s):
+    return lib().qo_cr_value(np.ascontiguousarray(p, np.float64), float(s))
+
+
+def cr_slope(p, s):
+    return lib().qo_cr_slope(np.ascontiguousarray(p, np.float64), float(s))
+
+
+def pinning(kind, strength, seed, did, j, u):
+    return lib().qo_pinning(int(kind), float(strength), int(seed), int(did), int(j), float(u))
+
+
+def potential(strength, seed, did, j, u):
+    return lib().qo_potential(float(strength), int(seed), int(did), int(j), float(u))
+
+
+def forces(kind, strength, seed, did, c, f, u):
+    u = np.ascontiguousarray(u, np.float64)
+    F = np.zeros_like(u)
+    lib().qo_forces(int(kind), float(strength), int(seed), int(did), u.size, float(c),
+                    float(f), u, F)
+    return F
+
+
+def measure(u, F):
+    u = np.ascontiguousarray(u, np.float64)
+    F = np.ascontiguousarray(F, np.float64)
+    v, ub, w2 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().qo_measure(u.size, u, F, ctypes.byref(v), ctypes.byref(ub), ctypes.byref(w2))
+    return v.value, ub.value, w2.value
+
+
+def euler(dt, u, F):
+    u = np.ascontiguousarray(u, np.float64)
+    F = np.ascontiguousarray(F, np.float64)
+    out = np.zeros_like(u)
+    lib().qo_euler(u.size, float(dt), u, F, out)
+    return out
+
+
+def run_sample(kind, strength, seed, did, L, c, dt, f, n_steps, meas_steps,
+               u0=None, step0=0):
+    """Evolve one sample; returns dict(v, ubar, w2, u) (u = state at n_steps)."""
+    meas = np.ascontiguousarray(meas_steps, np.int64)
+    u = np.zeros(int(L), np.float64) if u0 is None else np.array(u0, np.float64, copy=True)
+    v = np.full(meas.size, np.nan)
+    ub = np.full(meas.size, np.nan)
+    w2 = np.full(meas.size, np.nan)
+    rc = lib().qo_run(int(kind), float(strength), int(seed), int(did), int(L), float(c),
+                      float(dt), float(f), int(step0), int(n_steps), meas,
+                      int(meas.size), u, v, ub, w2)
+    if rc != 0:
+        raise ValueError("oracle qo_run rejected its input")
+    return {"v": v, "ubar": ub, "w2": w2, "u": u}
+
+
+def run(problem, u0=None, step0=0):
+    """Run every sample of a problem dict (see paper_1211_7275_amd.workloads).
+
+    Returns per-sample series [S][n_meas] for v, ubar, w2 and the final states
+    (list of arrays).  Ensemble averages give each sample equal weight.
+    """
+    S = len(problem["L"])
+    meas = np.asarray(problem["meas_steps"], np.int64)
+    out = {k: np.zeros((S, meas.size)) for k in ("v", "ubar", "w2")}
+    states = []
+    for s in range(S):
+        r = run_sample(problem["kind"], problem["strength"], problem["seed"],
+                       problem["disorder_id"][s], problem["L"][s], problem["c"],
+                       problem["dt"], problem["f"][s], problem["n_steps"], meas,
+                       None if u0 is None else u0[s], step0)
+        for k in ("v", "ubar", "w2"):
+            out[k][s] = r[k]
+        states.append(r["u"])
+    out["u"] = states
+    return out
