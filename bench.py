@@ -1,0 +1,227 @@
+"""Benchmark of the QEW hot path on one MI355X.
+
+Workload: L = 2^22 sites x 4 random-field samples (uniform values, Catmull-Rom
+spline), c = 1, dt = 0.05, f = 1.0, flat start, with the measurement cadence
+of 200 log-spaced points over 10^6 steps (those that fall inside the timed
+horizon).  A benchmark "step" is one Euler step of all four chains
+(4 * 2^22 site updates), measurements included.  Inputs are synthetic and
+generated on the device (the disorder is counter-based; the state starts flat).
+
+The timed path is the FP32-split fused (temporally blocked) kernel; the FP64
+plain one-step kernel is timed beside it on the same workload.  The oracle
+(FP64, CPU) is timed on a bounded sample of the same workload on the host.
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1211_7275_amd import workloads  # noqa: E402
+
+# MI355X (gfx950) figures used for the rooflines.
+CUS = 256
+CLOCK_HZ = 2.4e9
+VALU_LANE_OPS = CUS * 4 * 16 * CLOCK_HZ     # 4 SIMD x 16 lanes per CU per clock = 39.3e12
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic VALU operations of one FP32 split site update:
+# Laplacian on (cell, offset) 7, Catmull-Rom from the four cached nodes 12,
+# total force 2, Euler 1, renormalisation 7.
+OPS_SITE_UPDATE_RF = 29
+OPS_SITE_UPDATE_RB = 28
+# One node: Philox4x32-10 (10 rounds x (2 64-bit products + 2 three-input
+# xors + 2 key adds)) = 60, plus the value conversion (RF 3, RB 8).
+OPS_NODE_RF = 63
+OPS_NODE_RB = 68
+# FP64 plain update: 4 nodes + FP64 spline/stencil/Euler (~30).
+HORIZON = 1_000_000
+N_POINTS = 200
+
+
+def bench_problem(steps, L=1 << 22, samples=4):
+    p = workloads.config3(n_steps=HORIZON, n_meas=N_POINTS, samples=samples, L=L)
+    meas = p["meas_steps"]
+    p["n_steps"] = int(steps)
+    p["meas_steps"] = meas[meas <= steps]
+    return p
+
+
+def time_path(qew, p, precision, path, warm_steps, k=0, tile=0):
+    import torch
+
+    pw = dict(p, n_steps=int(warm_steps), meas_steps=p["meas_steps"][p["meas_steps"] <= warm_steps])
+    warm = qew.Simulation(pw, precision=precision, path=path, k=k, tile=tile)
+    warm.run()
+    info = warm.info()
+    warm.close()
+    sim = qew.Simulation(p, precision=precision, path=path, k=info.k if path else 0,
+                         tile=info.tile if path else 0, flags=qew.QEW_FLAG_TIMING)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = sim.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sim.stats()
+    info = sim.info()
+    sim.close()
+    return out, st, info, t1 - t0
+
+
+def fused_roofline(kind, st, info, out, steps):
+    """ALU roofline of the fused kernel from HIP-event launch durations."""
+    sites = info.total_sites
+    # Cells entered per site update (physics, not implementation): the centre
+    # of mass advanced by ubar(last) - ubar(0) cells over the timed steps.
+    ub = out["ubar"]
+    adv = float(np.nanmean(ub[:, -1])) if ub.shape[1] else 0.0
+    entries_per_update = max(adv, 0.0) / max(steps, 1)
+    per_update = (OPS_SITE_UPDATE_RF if kind == 0 else OPS_SITE_UPDATE_RB) + \
+        (OPS_NODE_RF if kind == 0 else OPS_NODE_RB) * entries_per_update
+    launch_ms = st.step_ms / max(st.step_launches, 1)
+    updates_per_launch = sites * steps / max(st.step_launches, 1)
+    achieved = per_update * updates_per_launch / (launch_ms * 1e-3) / 1e12
+    peak = VALU_LANE_OPS / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "ops_per_update": round(per_update, 3), "launch_ms": round(launch_ms, 5),
+            "k": info.k, "tile": info.tile}
+
+
+def plain_roofline(st, info, steps):
+    """HBM roofline of the FP64 plain one-step kernel (16 B per site update)."""
+    launch_ms = st.step_ms / max(st.step_launches, 1)
+    bytes_per_launch = 16.0 * info.total_sites * steps / max(st.step_launches, 1)
+    gbs = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "launch_ms": round(launch_ms, 5)}
+
+
+def cpu_baseline(p, seconds_target=15.0):
+    from oracle import oracle
+
+    threads = oracle.get_threads()
+    L = int(p["L"][0])
+    # one sample, full length, as many steps as fit the time target
+    t0 = time.perf_counter()
+    oracle.run_sample(p["kind"], p["strength"], p["seed"], 0, L, p["c"], p["dt"], 1.0, 1, [])
+    per_step = time.perf_counter() - t0
+    steps = max(1, int(seconds_target / max(per_step, 1e-6)))
+    t0 = time.perf_counter()
+    oracle.run_sample(p["kind"], p["strength"], p["seed"], 0, L, p["c"], p["dt"], 1.0, steps, [])
+    dt = time.perf_counter() - t0
+    return {"value": round(L * steps / dt, 1), "unit": "site-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"1 of the 4 samples (L=2^22), {steps} Euler steps from the flat start, "
+                      f"FP64, OpenMP over sites, {dt:.1f} s"}
+
+
+def parity_check(qew):
+    """Error of both GPU paths against the oracle on a small case (L=1024 x 2, 2000 steps)."""
+    from oracle import oracle
+
+    p = workloads.config0(n_steps=2000, n_meas=20, samples=2)
+    ref = oracle.run(p)
+    res = {}
+    for name, prec, path in (("fp32_split_fused", qew.QEW_FP32_SPLIT, qew.QEW_FUSED),
+                             ("fp64_plain", qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP)):
+        sim = qew.Simulation(p, precision=prec, path=path)
+        out = sim.run()
+        err = max(float(np.max(np.abs(sim.read_state(s)[0] - ref["u"][s]))) for s in range(2))
+        sim.close()
+        res[name] = {"max_site_abs_err": err,
+                     "max_v_rel_err": float(np.max(np.abs(out["v"] - ref["v"]) / np.abs(ref["v"])))}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100_000)
+    ap.add_argument("--warmup", type=int, default=512)
+    ap.add_argument("--plain-steps", type=int, default=2000)
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-parity", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (HBM counter calibration) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                                   "run with --gpus 1 (multi-GPU sharding is not built)"}))
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_calibration:
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                          "launches": 5}))
+        return
+
+    from paper_1211_7275_amd import qew
+
+    p = bench_problem(args.steps)
+    out, st, info, wall = time_path(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, args.warmup,
+                                    k=args.k, tile=args.tile)
+    sites = info.total_sites
+    value = sites * args.steps / wall
+    roof = fused_roofline(p["kind"], st, info, out, args.steps)
+    line = {
+        "metric": "site-updates/s FP32-split batched vs FP64 plain at L=2^22; % VALU/HBM roofline",
+        "value": round(value, 1),
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (counter-based Philox disorder generated on the device, flat start)",
+        "config": {
+            "workload": "L=2^22 x 4 samples, random field uniform(-1,1) Catmull-Rom, c=1, dt=0.05, "
+                        "f=1.0, measurement cadence of 200 log-spaced points over 10^6 steps",
+            "L": int(p["L"][0]), "samples": len(p["L"]), "steps": args.steps,
+            "measurements": int(len(p["meas_steps"])),
+            "path": "fp32-split fused temporally blocked", "k": info.k, "tile": info.tile,
+        },
+        "roofline": roof,
+    }
+    if not args.skip_plain:
+        pp = bench_problem(args.plain_steps)
+        out2, st2, info2, wall2 = time_path(qew, pp, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 64)
+        line["fp64_plain"] = {
+            "value": round(info2.total_sites * args.plain_steps / wall2, 1),
+            "unit": "site-updates/s", "steps": args.plain_steps,
+            "ms_per_step": round(wall2 * 1e3 / args.plain_steps, 6),
+            "roofline": plain_roofline(st2, info2, args.plain_steps),
+        }
+        line["speedup_vs_fp64_plain"] = round(value / line["fp64_plain"]["value"], 3)
+    if not args.skip_parity:
+        line["error_vs_oracle"] = parity_check(qew)
+    if not args.skip_cpu:
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * qew.h -- C ABI of libqew, the MI355X (gfx950) engine for the non-steady
+ * relaxation of a driven elastic line in a random medium: the quenched
+ * Edwards-Wilkinson (QEW) equation of Ferrero, Bustingorry and Kolton,
+ * "Non-steady relaxation and critical exponents at the depinning transition"
+ * (arXiv:1211.7275).
+ *
+ * What the library computes (the paper's method, Secs. II and III B):
+ *   - Eq. (1) with eta = 1, discretised in x with dx = 1 on a periodic chain
+ *     of L sites and integrated by the explicit Euler method (Sec. III B):
+ *       u_j <- u_j + dt * [ c (u_{j+1} + u_{j-1} - 2 u_j) + f + F_p(j, u_j) ]
+ *     synchronously over all sites, from the flat start u_j = 0 (Sec. II).
+ *   - F_p: random values at the integer points (j, n) of the (x, u) plane,
+ *     generated on demand (the paper's memory-free disorder, Sec. IV D) and
+ *     interpolated in u by a cubic (Catmull-Rom) spline (Sec. III B).  Random
+ *     field: the values are forces, uniform in (-1, 1).  Random bond: the
+ *     values are potential energies, N(0, 1), and F_p = -dU/du (Sec. II).
+ *     Values are scaled by `strength`.  Generator: Philox4x32-10 (Salmon et
+ *     al., SC'11) with counter (j, (uint32) n, disorder_id, 0) and key
+ *     (seed low word, seed high word).
+ *   - Observables of Sec. II, Eqs. (3)-(5), per sample s at every requested
+ *     measurement step m: v_s(m) = mean over j of the total force at step m
+ *     (equal to the mean of du/dt), ubar_s(m) = mean of u_j, and
+ *     w2_s(m) = mean of (u_j - ubar_s)^2, all accumulated in FP64.  The
+ *     disorder average (the overbar of Eqs. (3)-(5)) is the mean over samples,
+ *     which the caller forms from the per-sample series.
+ *
+ * Conventions for every call:
+ *   - Device pointers (`d_` prefix, and the workspace) are HIP device
+ *     memory owned by the caller; host pointers (`h_` prefix and the
+ *     problem's arrays) are ordinary host memory owned by the caller.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Every call returns a qew_status; nothing aborts and no C++ exception
+ *     crosses the ABI.  On failure qew_last_error() returns a message,
+ *     thread-local and valid until the next call on that thread.
+ *   - All validation of a problem happens in qew_plan, on the host, with no
+ *     device call, so it can be tested without a GPU.
+ */
+#ifndef QEW_H
+#define QEW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qew_status;
+#define QEW_OK            0
+#define QEW_EINVAL       (-1) /* bad argument or problem; nothing was launched      */
+#define QEW_ENOMEM       (-2) /* workspace smaller than qew_workspace_bytes()       */
+#define QEW_EDEVICE      (-3) /* HIP error; workspace contents undefined, plan valid */
+#define QEW_EUNSUPPORTED (-4) /* valid but not implemented combination             */
+
+/* disorder kinds (Sec. III B; RF = random field, RB = random bond) */
+#define QEW_RF_CR_UNIFORM 0   /* force values uniform in (-1,1), Catmull-Rom in u     */
+#define QEW_RB_CR_GAUSS   1   /* potential values N(0,1), Catmull-Rom, F_p = -dU/du   */
+
+/* arithmetic of the integrator */
+#define QEW_FP64_PLAIN 0      /* u in FP64                                             */
+#define QEW_FP32_SPLIT 1      /* u = int32 cell + FP32 offset in [0,1); FP64 sums     */
+
+/* kernel path */
+#define QEW_ONE_STEP 0        /* one Euler step per launch, all 4 nodes regenerated    */
+#define QEW_FUSED    1        /* k Euler steps per launch on register tiles with halos */
+
+/* qew_problem.flags */
+#define QEW_FLAG_NO_GRAPH 1   /* launch every kernel directly instead of replaying hipGraphs */
+#define QEW_FLAG_TIMING   2   /* record hipEvents around the stepping kernels (qew_run_stats) */
+
+/*
+ * One batch of independent samples sharing c, dt, disorder kind/strength,
+ * seed and measurement steps (the paper's parameters: L and dx = 1 in
+ * Sec. III B; c, eta = 1 and f in Eq. (1); RF/RB and the value distribution
+ * in Sec. II; independent disorder realisations averaged by the overbar).
+ * Arrays are read only during qew_plan (copied into the plan).
+ */
+typedef struct qew_problem {
+  int32_t         n_samples;    /* S >= 1                                               */
+  int32_t         kind;         /* QEW_RF_CR_UNIFORM or QEW_RB_CR_GAUSS                 */
+  const int64_t  *L;            /* [S] chain lengths, 3 <= L_s <= 2^30                  */
+  const double   *f;            /* [S] drive per sample (finite)                        */
+  const uint32_t *disorder_id;  /* [S] Philox counter word 2; equal ids => same disorder */
+  double          c;            /* elastic constant, > 0                                */
+  double          dt;           /* Euler time step, > 0, with c * dt <= 0.5             */
+  double          strength;     /* >= 0; multiplies the random values (0 => F_p = 0)    */
+  uint64_t        seed;         /* Philox key (low word, high word)                     */
+  int64_t         n_steps;      /* >= 0 Euler steps                                     */
+  const int64_t  *meas_steps;   /* [n_meas] strictly increasing, each in [0, n_steps]   */
+  int32_t         n_meas;       /* >= 0                                                 */
+  int32_t         precision;    /* QEW_FP64_PLAIN or QEW_FP32_SPLIT                     */
+  int32_t         path;         /* QEW_ONE_STEP, or QEW_FUSED (FP32 split only)         */
+  int32_t         k;            /* fused: steps per launch, 1..64 (0 = autotune)        */
+  int32_t         tile;         /* fused: sites per wave tile, 512/1024/2048 (0 = autotune); 4k <= tile */
+  int32_t         flags;        /* QEW_FLAG_* bits                                      */
+} qew_problem;
+
+typedef struct qew_plan_s qew_plan_t;
+
+/* What a plan resolved to (after autotuning, if any). */
+typedef struct qew_plan_info {
+  int64_t total_sites;   /* sum of L_s                                   */
+  int64_t padded_sites;  /* sites held per state buffer (64-site aligned) */
+  int32_t n_tiles;       /* work items of the stepping kernel            */
+  int32_t n_meas_tiles;  /* work items of the measurement kernels        */
+  int32_t k;             /* steps per fused launch (1 for one-step)      */
+  int32_t tile;          /* sites per fused wave tile (0 for one-step)   */
+  int32_t autotuned;     /* 1 if k / tile were chosen by qew_autotune    */
+  int32_t pad_;
+  int64_t cur_step;      /* step index of the state in the workspace     */
+} qew_plan_info;
+
+/* Timings of the last qew_run with QEW_FLAG_TIMING (HIP events on `stream`). */
+typedef struct qew_run_stats {
+  double  total_ms;        /* the whole qew_run on the stream                          */
+  double  step_ms;         /* summed duration of the stepping-kernel segments          */
+  double  meas_ms;         /* summed duration of the measurement kernels               */
+  int64_t step_launches;   /* stepping-kernel launches (graph nodes included)          */
+  int64_t meas_launches;   /* measurement points taken                                 */
+  int64_t site_updates;    /* sum_s L_s * (Euler steps advanced)                       */
+  int64_t graph_launches;  /* hipGraphLaunch calls                                     */
+} qew_run_stats;
+
+/*
+ * Validate a problem and build a plan (host only; no device call).
+ * Copies every array.  *out receives a plan to free with qew_plan_destroy.
+ * Errors: QEW_EINVAL (any constraint in qew_problem violated, NULL pointers),
+ * QEW_EUNSUPPORTED (FUSED with FP64_PLAIN).
+ */
+qew_status qew_plan(const qew_problem *problem, qew_plan_t **out);
+
+/* Bytes of device workspace qew_run needs for this plan (0 if plan is NULL). */
+size_t qew_workspace_bytes(const qew_plan_t *plan);
+
+/* Fill *info (host pointer). */
+qew_status qew_plan_info_get(const qew_plan_t *plan, qew_plan_info *info);
+
+/*
+ * Choose k and the tile width of the fused path by timing short runs on the
+ * workspace (its state is overwritten).  Called by qew_run by itself when the
+ * problem left k or tile at 0.  No-op for the one-step path.
+ */
+qew_status qew_autotune(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * Run the problem (Eq. (1) by Euler steps, Sec. III B) and measure Eqs. (3)-(5).
+ *   resume = 0: flat start u = 0 at step 0 (Sec. II).
+ *   resume = 1: continue from the state and step left in this workspace by
+ *               the previous qew_run or qew_write_state (QEW_EINVAL if none).
+ * The run ends at problem.n_steps.  h_v, h_w2, h_ubar are host arrays
+ * [S][n_meas] (row = sample); entries whose step is below the starting step
+ * are left untouched.  Any of them may be NULL.  Synchronous: returns after
+ * the stream has drained.  d_ws must be 256-byte aligned and hold at least
+ * qew_workspace_bytes(plan) bytes (else QEW_ENOMEM).
+ */
+qew_status qew_run(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *stream, int32_t resume,
+                   double *h_v, double *h_w2, double *h_ubar);
+
+/* Statistics of the last qew_run of this plan (host pointer). */
+qew_status qew_run_stats_get(const qew_plan_t *plan, qew_run_stats *stats);
+
+/*
+ * Copy sample s's state (step index `*h_step`) to h_u [L_s] as FP64
+ * (cell + offset for the split precision).  Synchronous.
+ */
+qew_status qew_read_state(const qew_plan_t *plan, const void *d_ws, void *stream, int32_t s,
+                          double *h_u, int64_t *h_step);
+
+/*
+ * Overwrite sample s's state with h_u [L_s] and set the step index of the
+ * whole workspace to `step` (checkpoint restore, tests).  Split precision:
+ * cell = floor(u), offset = u - cell rounded to FP32 (an offset that rounds
+ * to 1 moves to the next cell).  The next qew_run must use resume = 1.
+ * Synchronous.
+ */
+qew_status qew_write_state(qew_plan_t *plan, void *d_ws, void *stream, int32_t s,
+                           const double *h_u, int64_t step);
+
+/*
+ * Debug: Philox4x32-10 of N counters.  d_ctr, d_out: device [N][4] uint32;
+ * key = (seed low word, seed high word).  Asynchronous on `stream`.
+ */
+qew_status qew_debug_philox_fill(const uint32_t *d_ctr, uint64_t seed, uint32_t *d_out,
+                                 int64_t N, void *stream);
+
+/*
+ * Debug: pinning force F_p at N points, in the arithmetic of `precision`.
+ * Point i: column d_j[i], disorder id d_did[i], u = d_cell[i] + d_frac[i]
+ * (FP64 path: u formed in FP64 then floored; split path: cell as given and
+ * offset rounded to FP32, which must lie in [0, 1)).  d_out: device [N] FP64.
+ * Asynchronous on `stream`.
+ */
+qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, int32_t precision,
+                                const uint32_t *d_did, const int32_t *d_j, const int32_t *d_cell,
+                                const double *d_frac, double *d_out, int64_t N, void *stream);
+
+/* Free a plan (NULL is allowed); releases its hipGraphs. */
+void qew_plan_destroy(qew_plan_t *plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *qew_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QEW_H */

@@ -53,6 +53,11 @@ def lib():
     L.qo_run.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d, c_d, c_d, c_i64, c_i64,
                          i64p, ctypes.c_int32, f64p, f64p, f64p, f64p]
     L.qo_run.restype = c_int
+    L.qo_run_window.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_i64, c_i64, c_d, c_d, c_d,
+                                c_i64, f64p]
+    L.qo_run_window.restype = c_int
+    L.qo_mean_node.argtypes = [c_int, c_u64, c_u32, c_i64, c_i64]
+    L.qo_mean_node.restype = c_d
     L.qo_set_threads.argtypes = [c_int]
     L.qo_get_threads.restype = c_int
     _lib = L
@@ -141,6 +146,26 @@ def run_sample(kind, strength, seed, did, L, c, dt, f, n_steps, meas_steps,
     if rc != 0:
         raise ValueError("oracle qo_run rejected its input")
     return {"v": v, "ubar": ub, "w2": w2, "u": u}
+
+
+def site_after(kind, strength, seed, did, L, j, c, dt, f, n_steps):
+    """u_j after n_steps from the flat start on the periodic chain of length L,
+    computed on the light-cone window of sites j - n_steps - 1 .. j + n_steps + 1."""
+    half = int(n_steps) + 1
+    W = 2 * half + 1
+    if W >= L:
+        r = run_sample(kind, strength, seed, did, L, c, dt, f, n_steps, [])
+        return r["u"][int(j)]
+    u = np.zeros(W, np.float64)
+    rc = lib().qo_run_window(int(kind), float(strength), int(seed), int(did), int(L),
+                             int(j) - half, W, float(c), float(dt), float(f), int(n_steps), u)
+    if rc != 0:
+        raise ValueError("oracle qo_run_window rejected its input")
+    return u[half]
+
+
+def mean_node(kind, seed, did, L, n):
+    return lib().qo_mean_node(int(kind), int(seed), int(did), int(L), int(n))
 
 
 def run(problem, u0=None, step0=0):

@@ -258,6 +258,60 @@ int qo_run(int kind, double strength, uint64_t seed, uint32_t disorder_id,
     return 0;
 }
 
+/*
+ * Light-cone window of a long chain.  One Euler step of the discretised
+ * Eq. (1) couples a site only to its two neighbours, so site j after m steps
+ * depends on the state and the disorder within distance m of j and on
+ * nothing else.  This evolves W consecutive sites whose column indices (the
+ * Philox counter word j) are (j0 + i) mod L_global, i = 0..W-1, closing the
+ * window on itself at its ends.  The closure is wrong only within distance m
+ * of the two ends after m steps; sites i in [m, W - m) are those of the full
+ * periodic chain of length L_global.  `u` holds the window's state on entry
+ * and on return.  Returns 0, or -1 on bad input.
+ */
+int qo_run_window(int kind, double strength, uint64_t seed, uint32_t disorder_id,
+                  int64_t L_global, int64_t j0, int64_t W, double c, double dt, double f,
+                  int64_t n_steps, double *u)
+{
+    if (W < 3 || L_global < 1 || n_steps < 0) return -1;
+    double *F = (double *)malloc((size_t)W * sizeof(double));
+    double *un = (double *)malloc((size_t)W * sizeof(double));
+    if (!F || !un) { free(F); free(un); return -1; }
+    for (int64_t m = 0; m < n_steps; ++m) {
+        int64_t i;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (i = 0; i < W; ++i) {
+            int64_t im = (i == 0) ? W - 1 : i - 1;
+            int64_t ip = (i == W - 1) ? 0 : i + 1;
+            int64_t j = ((j0 + i) % L_global + L_global) % L_global;
+            double lap = (u[ip] + u[im]) - 2.0 * u[i];
+            double fp = qo_pinning(kind, strength, seed, disorder_id, j, u[i]);
+            F[i] = ((c * lap) + f) + fp;
+        }
+        qo_euler(W, dt, u, F, un);
+        memcpy(u, un, (size_t)W * sizeof(double));
+    }
+    free(F);
+    free(un);
+    return 0;
+}
+
+/* Mean over j in [0, L) of the unscaled node value R(j, n) (Neumaier sum). */
+double qo_mean_node(int kind, uint64_t seed, uint32_t disorder_id, int64_t L, int64_t n)
+{
+    double s = 0.0, comp = 0.0;
+    for (int64_t j = 0; j < L; ++j) {
+        double x = qo_node(kind, seed, disorder_id, j, n);
+        double t = s + x;
+        if (fabs(s) >= fabs(x)) comp += (s - t) + x;
+        else comp += (x - t) + s;
+        s = t;
+    }
+    return (s + comp) / (double)L;
+}
+
 /* Thread control for the OpenMP site loop (1 = serial). */
 void qo_set_threads(int n)
 {

@@ -1,0 +1,73 @@
+// qew_internal.hpp -- interface between the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qew {
+
+// Device-resident tables of a plan (all pointers into the workspace).
+struct Tables {
+  const int64_t* off;       // [S] first site of sample s in a state buffer
+  const int32_t* L;         // [S] chain length
+  const double* f;          // [S] drive (FP64 path)
+  const float* f32;         // [S] drive rounded to FP32 (split path)
+  const uint32_t* did;      // [S] disorder id
+  const int32_t* mt_s;      // [n_mt] measurement / one-step tiles: sample
+  const int32_t* mt_p0;     //        first site
+  const int32_t* mt_len;    //        sites
+  const int32_t* mt_first;  // [S+1] first measurement tile of each sample
+  const int32_t* ft_s;      // [n_ft] fused wave tiles: sample
+  const int32_t* ft_p0;     //        first valid site
+  const int32_t* ft_len;    //        valid sites
+  int32_t n_mt;
+  int32_t n_ft;
+};
+
+struct SplitBuf {
+  int32_t* cell;   // [padded sites] integer part of u
+  float* frac;     // [padded sites] u - cell in [0, 1)
+  float4* nodes;   // [padded sites] nodes cell-1 .. cell+2 of each site (fused path only)
+};
+
+struct Phys {
+  double c, dt, strength;
+  float cf, dtf, sgn_strf;  // FP32 copies; sgn_strf = +strength (RF) or -strength (RB)
+  uint32_t k0, k1;          // Philox key (seed words)
+};
+
+// Measurement partial of one tile: sum of F, sum of (u - K), sum of (u - K)^2, K.
+struct Partial {
+  double sum_f, s1, s2, shift;
+};
+
+constexpr int kMeasTile = 4096;   // sites per measurement / one-step tile
+constexpr int kBlock = 256;       // threads per workgroup of every kernel
+constexpr int kMaxHalo = 64;
+
+// Launchers (return the launch error; all asynchronous on `st`).
+hipError_t launch_init_plain(const Tables& t, double* u, hipStream_t st);
+hipError_t launch_init_split(const Tables& t, SplitBuf b, const Phys& ph, int kind, bool nodes,
+                             hipStream_t st);
+hipError_t launch_refresh_nodes(const Tables& t, SplitBuf b, const Phys& ph, int kind,
+                                hipStream_t st);
+hipError_t launch_step_plain(const Tables& t, const double* uin, double* uout, const Phys& ph,
+                             int kind, hipStream_t st);
+hipError_t launch_step_split1(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
+                              hipStream_t st);
+hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
+                             int tile, int halo, int nsub, int grid, hipStream_t st);
+int fused_max_grid(int tile);
+hipError_t launch_meas_plain(const Tables& t, const double* u, const Phys& ph, int kind,
+                             Partial* part, hipStream_t st);
+hipError_t launch_meas_split(const Tables& t, SplitBuf b, const Phys& ph, int kind, Partial* part,
+                             hipStream_t st);
+hipError_t launch_meas_final(const Tables& t, int n_samples, const Partial* part, int meas_index,
+                             int n_meas, double* series, hipStream_t st);
+hipError_t launch_philox_fill(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
+                              int64_t n, hipStream_t st);
+hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int precision,
+                             const uint32_t* did, const int32_t* j, const int32_t* cell,
+                             const double* frac, double* out, int64_t n, hipStream_t st);
+
+}  // namespace qew

@@ -1,0 +1,608 @@
+// qew_kernels.hip -- gfx950 kernels of the QEW integrator.
+//
+// Eq. (1) of arXiv:1211.7275 (eta = 1) on periodic chains, explicit Euler
+// (Sec. III B), pinning force from counter-based random values at integer u
+// with a Catmull-Rom spline, and the FP64 observables of Eqs. (3)-(5).
+//
+// Kernels:
+//   k_step_plain   one FP64 Euler step per launch, one thread per site, four
+//                  Philox nodes regenerated per site update.  HBM traffic is
+//                  16 B per update (read u, write u; neighbours hit L1/L2).
+//   k_step_split1  the same on the split state (int32 cell + FP32 offset).
+//   k_step_fused   `nsub` split Euler steps per launch.  Each wave owns a tile
+//                  of 64*P consecutive sites held in registers (P per lane),
+//                  `halo` of them on each side recomputed redundantly, and
+//                  each site keeps the four nodes of its cell in registers
+//                  (and in HBM between launches).  A site whose cell changes
+//                  needs one new node; the wave gathers those requests into
+//                  LDS, generates them with all 64 lanes, and scatters them
+//                  back, so Philox costs about one wave pass per sub-step
+//                  instead of one per changed site slot.
+//   k_meas_*       per-tile FP64 partials of sum F, sum (u-K), sum (u-K)^2.
+//   k_meas_final   per-sample combine (Chan et al. pairwise update) into
+//                  v, ubar, w2.
+#include "qew_device.hpp"
+#include "qew_internal.hpp"
+
+namespace qew {
+
+namespace {
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Orders this wave's LDS accesses (all lanes) before and after the point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Block-wide deterministic FP64 sum of three values (fixed reduction order).
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* lds /*[3*4]*/) {
+  a = wave_sum_f64(a);
+  b = wave_sum_f64(b);
+  c = wave_sum_f64(c);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    lds[w * 3 + 0] = a;
+    lds[w * 3 + 1] = b;
+    lds[w * 3 + 2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+      x += lds[i * 3 + 0];
+      y += lds[i * 3 + 1];
+      z += lds[i * 3 + 2];
+    }
+    a = x;
+    b = y;
+    c = z;
+  }
+}
+
+// Position in the sample of a lane's i-th site (pos0 < L).
+__device__ __forceinline__ int site_of(int pos0, int i, int L, bool tiny) {
+  int j = pos0 + i;
+  if (tiny) return j % L;
+  return j >= L ? j - L : j;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Initialisation: flat start u = 0 (Sec. II).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_init_plain(Tables t, double* u) {
+  const int tile = blockIdx.x;
+  const int s = t.mt_s[tile];
+  const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
+  const int64_t base = t.off[s];
+  for (int q = threadIdx.x; q < len; q += kBlock) u[base + p0 + q] = 0.0;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kBlock)
+    k_init_split(Tables t, SplitBuf b, Phys ph, int with_nodes, int keep_state) {
+  const int tile = blockIdx.x;
+  const int s = t.mt_s[tile];
+  const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
+  const int64_t base = t.off[s];
+  const uint32_t id = t.did[s];
+  for (int q = threadIdx.x; q < len; q += kBlock) {
+    const int j = p0 + q;
+    int32_t c = 0;
+    if (keep_state) {
+      c = b.cell[base + j];
+    } else {
+      b.cell[base + j] = 0;
+      b.frac[base + j] = 0.0f;
+    }
+    if (with_nodes) {
+      float4 nd;
+      nd.x = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1);
+      nd.y = node_f32<KIND>(j, c, id, ph.k0, ph.k1);
+      nd.z = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1);
+      nd.w = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1);
+      b.nodes[base + j] = nd;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-step kernels (one Euler step per launch).
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ void __launch_bounds__(kBlock)
+    k_step_plain(Tables t, const double* __restrict__ uin, double* __restrict__ uout, Phys ph) {
+  const int tile = blockIdx.x;
+  const int s = t.mt_s[tile];
+  const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
+  const int L = t.L[s];
+  const int64_t base = t.off[s];
+  const uint32_t id = t.did[s];
+  const double f = t.f[s];
+  const PlainPhys pp{ph.c, ph.dt, ph.strength};
+  for (int q = threadIdx.x; q < len; q += kBlock) {
+    const int j = p0 + q;
+    const int jm = (j == 0) ? L - 1 : j - 1;
+    const int jp = (j == L - 1) ? 0 : j + 1;
+    const double u = uin[base + j];
+    const double F = plain_force<KIND>(uin[base + jm], u, uin[base + jp], (uint32_t)j, id, ph.k0,
+                                       ph.k1, f, pp);
+    uout[base + j] = u + ph.dt * F;
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ void nodes_of(uint32_t j, int32_t c, uint32_t id, const Phys& ph,
+                                         float& p0, float& p1, float& p2, float& p3) {
+  if (ph.strength == 0.0) {
+    p0 = p1 = p2 = p3 = 0.0f;
+    return;
+  }
+  p0 = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1);
+  p1 = node_f32<KIND>(j, c, id, ph.k0, ph.k1);
+  p2 = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1);
+  p3 = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, SplitBuf out, Phys ph) {
+  const int tile = blockIdx.x;
+  const int s = t.mt_s[tile];
+  const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
+  const int L = t.L[s];
+  const int64_t base = t.off[s];
+  const uint32_t id = t.did[s];
+  const float f = t.f32[s];
+  const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
+  for (int q = threadIdx.x; q < len; q += kBlock) {
+    const int j = p0 + q;
+    const int jm = (j == 0) ? L - 1 : j - 1;
+    const int jp = (j == L - 1) ? 0 : j + 1;
+    int32_t c = in.cell[base + j];
+    float r = in.frac[base + j];
+    float n0, n1, n2, n3;
+    nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+    const float F = split_force<KIND>(c, r, in.cell[base + jm], in.frac[base + jm],
+                                      in.cell[base + jp], in.frac[base + jp], n0, n1, n2, n3, f, sp);
+    split_advance(c, r, F, sp.dt);
+    out.cell[base + j] = c;
+    out.frac[base + j] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused temporally blocked kernel (split precision).
+// ---------------------------------------------------------------------------
+template <int KIND, int P>
+__global__ void __launch_bounds__(kBlock)
+    k_step_fused(Tables t, SplitBuf in, SplitBuf out, Phys ph, int halo, int nsub) {
+  __shared__ int2 s_task[kBlock / 64][64 * P];
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform_i32(threadIdx.x >> 6);
+  int2* task = s_task[wv];
+  const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
+  const int waves_in_grid = gridDim.x * (kBlock / 64);
+
+  for (int ti = blockIdx.x * (kBlock / 64) + wv; ti < t.n_ft; ti += waves_in_grid) {
+    const int s = uniform_i32(t.ft_s[ti]);
+    const int p0 = uniform_i32(t.ft_p0[ti]);
+    const int len = uniform_i32(t.ft_len[ti]);
+    const int L = uniform_i32(t.L[s]);
+    const int64_t base = uniform_i64(t.off[s]);
+    const uint32_t id = (uint32_t)uniform_i32((int)t.did[s]);
+    const float f = t.f32[s];
+
+    // First site of this lane, as a position in the sample (periodic).
+    int pos0 = (p0 - halo + lane * P) % L;
+    if (pos0 < 0) pos0 += L;
+    const bool tiny = L < P;  // wave-uniform: a lane's sites wrap more than once
+
+    int32_t c[P];
+    float r[P], n0[P], n1[P], n2[P], n3[P];
+    {
+      int pos = pos0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        c[i] = in.cell[base + pos];
+        r[i] = in.frac[base + pos];
+        const float4 nd = in.nodes[base + pos];
+        n0[i] = nd.x;
+        n1[i] = nd.y;
+        n2[i] = nd.z;
+        n3[i] = nd.w;
+        pos = (pos + 1 == L) ? 0 : pos + 1;
+      }
+    }
+
+    for (int sub = 0; sub < nsub; ++sub) {
+      // Neighbour values across lanes; the tile ends reflect (their garbage
+      // stays inside the halo, which moves inwards one site per sub-step).
+      int32_t cle = __shfl_up(c[P - 1], 1, 64);
+      float rle = __shfl_up(r[P - 1], 1, 64);
+      int32_t cre = __shfl_down(c[0], 1, 64);
+      float rre = __shfl_down(r[0], 1, 64);
+      if (lane == 0) {
+        cle = c[0];
+        rle = r[0];
+      }
+      if (lane == 63) {
+        cre = c[P - 1];
+        rre = r[P - 1];
+      }
+
+      int32_t pc = cle;
+      float pr = rle;
+      uint32_t up = 0u, dn = 0u, big = 0u;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int32_t nc = (i + 1 < P) ? c[i + 1] : cre;
+        const float nr = (i + 1 < P) ? r[i + 1] : rre;
+        const float F = split_force<KIND>(c[i], r[i], pc, pr, nc, nr, n0[i], n1[i], n2[i], n3[i],
+                                          f, sp);
+        const int32_t oc = c[i];
+        pc = oc;
+        pr = r[i];
+        split_advance(c[i], r[i], F, sp.dt);
+        const int32_t d = c[i] - oc;
+        up |= (uint32_t)(d == 1) << i;
+        dn |= (uint32_t)(d == -1) << i;
+        big |= (uint32_t)((d > 1) | (d < -1)) << i;
+      }
+
+      // Rare: a jump of two or more cells regenerates all four nodes.
+      if (__ballot(big != 0u)) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          if ((big >> i) & 1u) {
+            const int j = site_of(pos0, i, L, tiny);
+            nodes_of<KIND>((uint32_t)j, c[i], id, ph, n0[i], n1[i], n2[i], n3[i]);
+          }
+        }
+      }
+
+      // One new node per site that moved by one cell: gather the requests of
+      // the whole wave into LDS (lane-major, offsets from a wave prefix sum),
+      // generate them with all 64 lanes, and scatter them back.
+      const uint32_t chg = up | dn;
+      const uint32_t cnt = (uint32_t)__popc(chg);
+      uint32_t incl = cnt;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+      }
+      const uint32_t ntask = __builtin_amdgcn_readlane(incl, 63);
+      const uint32_t lane_base = incl - cnt;
+      if (ntask != 0u) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          if ((chg >> i) & 1u) {
+            const int j = site_of(pos0, i, L, tiny);
+            const int32_t need = ((up >> i) & 1u) ? c[i] + 2 : c[i] - 1;
+            task[lane_base + __popc(chg & ((1u << i) - 1u))] = make_int2(j, need);
+          }
+        }
+        wave_lds_sync();
+        for (uint32_t q = lane; q < ntask; q += 64) {
+          const int2 tk = task[q];
+          float v = 0.0f;
+          if (ph.strength != 0.0) v = node_f32<KIND>((uint32_t)tk.x, tk.y, id, ph.k0, ph.k1);
+          task[q].x = __float_as_int(v);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          if ((chg >> i) & 1u) {
+            const float v = __int_as_float(task[lane_base + __popc(chg & ((1u << i) - 1u))].x);
+            if ((up >> i) & 1u) {
+              n0[i] = n1[i];
+              n1[i] = n2[i];
+              n2[i] = n3[i];
+              n3[i] = v;
+            } else {
+              n3[i] = n2[i];
+              n2[i] = n1[i];
+              n1[i] = n0[i];
+              n0[i] = v;
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+
+    // Write the valid part: tile-local q in [halo, halo + len).
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int q = lane * P + i;
+      if (q >= halo && q < halo + len) {
+        const int64_t g = base + p0 + (q - halo);
+        out.cell[g] = c[i];
+        out.frac[g] = r[i];
+        out.nodes[g] = make_float4(n0[i], n1[i], n2[i], n3[i]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Measurement partials (Eqs. (3)-(5)) of the state at one step.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ void __launch_bounds__(kBlock)
+    k_meas_plain(Tables t, const double* __restrict__ u, Phys ph, Partial* part) {
+  __shared__ double lds[3 * (kBlock / 64)];
+  const int tile = blockIdx.x;
+  const int s = t.mt_s[tile];
+  const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
+  const int L = t.L[s];
+  const int64_t base = t.off[s];
+  const uint32_t id = t.did[s];
+  const double f = t.f[s];
+  const PlainPhys pp{ph.c, ph.dt, ph.strength};
+  const double K = floor(u[base + p0]);
+  double sf = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int q = threadIdx.x; q < len; q += kBlock) {
+    const int j = p0 + q;
+    const int jm = (j == 0) ? L - 1 : j - 1;
+    const int jp = (j == L - 1) ? 0 : j + 1;
+    const double uj = u[base + j];
+    sf += plain_force<KIND>(u[base + jm], uj, u[base + jp], (uint32_t)j, id, ph.k0, ph.k1, f, pp);
+    const double x = uj - K;
+    s1 += x;
+    s2 += x * x;
+  }
+  block_sum3(sf, s1, s2, lds);
+  if (threadIdx.x == 0) part[tile] = Partial{sf, s1, s2, K};
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phys ph, Partial* part) {
+  __shared__ double lds[3 * (kBlock / 64)];
+  const int tile = blockIdx.x;
+  const int s = t.mt_s[tile];
+  const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
+  const int L = t.L[s];
+  const int64_t base = t.off[s];
+  const uint32_t id = t.did[s];
+  const float f = t.f32[s];
+  const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
+  const int32_t K = b.cell[base + p0];
+  double sf = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int q = threadIdx.x; q < len; q += kBlock) {
+    const int j = p0 + q;
+    const int jm = (j == 0) ? L - 1 : j - 1;
+    const int jp = (j == L - 1) ? 0 : j + 1;
+    const int32_t c = b.cell[base + j];
+    const float r = b.frac[base + j];
+    float n0, n1, n2, n3;
+    nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+    const float F = split_force<KIND>(c, r, b.cell[base + jm], b.frac[base + jm], b.cell[base + jp],
+                                      b.frac[base + jp], n0, n1, n2, n3, f, sp);
+    sf += (double)F;
+    const double x = (double)(c - K) + (double)r;
+    s1 += x;
+    s2 += x * x;
+  }
+  block_sum3(sf, s1, s2, lds);
+  if (threadIdx.x == 0) part[tile] = Partial{sf, s1, s2, (double)K};
+}
+
+// Per-sample combine of tile partials: mean and sum of squared deviations by
+// the pairwise update of Chan, Golub and LeVeque, in a fixed order.
+struct Moments {
+  double n, mean, m2, sf;
+};
+
+__device__ __forceinline__ Moments combine(const Moments& a, const Moments& b) {
+  if (a.n == 0.0) return b;
+  if (b.n == 0.0) return a;
+  const double n = a.n + b.n;
+  const double d = b.mean - a.mean;
+  Moments r;
+  r.n = n;
+  r.mean = a.mean + d * (b.n / n);
+  r.m2 = (a.m2 + b.m2) + d * d * (a.n * b.n / n);
+  r.sf = a.sf + b.sf;
+  return r;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_meas_final(Tables t, const Partial* part, int meas_index, int n_meas, double* series) {
+  __shared__ Moments lds[kBlock];
+  const int s = blockIdx.x;
+  const int t0 = t.mt_first[s], t1 = t.mt_first[s + 1];
+  Moments acc{0.0, 0.0, 0.0, 0.0};
+  for (int ti = t0 + threadIdx.x; ti < t1; ti += kBlock) {
+    const Partial p = part[ti];
+    const double n = (double)t.mt_len[ti];
+    Moments m;
+    m.n = n;
+    m.mean = p.shift + p.s1 / n;
+    m.m2 = p.s2 - p.s1 * (p.s1 / n);
+    m.sf = p.sum_f;
+    acc = combine(acc, m);
+  }
+  lds[threadIdx.x] = acc;
+  __syncthreads();
+  for (int stride = kBlock / 2; stride >= 1; stride >>= 1) {
+    if ((int)threadIdx.x < stride) lds[threadIdx.x] = combine(lds[threadIdx.x], lds[threadIdx.x + stride]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const Moments m = lds[0];
+    const double L = (double)t.L[s];
+    double* out = series + ((int64_t)s * n_meas + meas_index) * 3;
+    out[0] = m.sf / L;
+    out[1] = m.mean;
+    out[2] = (m.m2 > 0.0 ? m.m2 : 0.0) / L;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Debug kernels.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+    k_philox_fill(const uint4* __restrict__ ctr, uint32_t k0, uint32_t k1, uint4* __restrict__ out,
+                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  uint4 x = ctr[i];
+  philox4x32_10(x.x, x.y, x.z, x.w, k0, k1);
+  out[i] = x;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kBlock)
+    k_force_eval(double strength, uint32_t k0, uint32_t k1, int precision,
+                 const uint32_t* __restrict__ did, const int32_t* __restrict__ jj,
+                 const int32_t* __restrict__ cell, const double* __restrict__ frac,
+                 double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t j = (uint32_t)jj[i];
+  const uint32_t id = did[i];
+  if (precision == 0) {
+    const double u = (double)cell[i] + frac[i];
+    const double nf = floor(u);
+    const int32_t c = (int32_t)nf;
+    double p[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = strength * node_f64<KIND>(j, c - 1 + q, id, k0, k1);
+    out[i] = spline_f64<KIND>(p, u - nf);
+  } else {
+    const int32_t c = cell[i];
+    const float r = (float)frac[i];
+    const float p0 = node_f32<KIND>(j, c - 1, id, k0, k1);
+    const float p1 = node_f32<KIND>(j, c, id, k0, k1);
+    const float p2 = node_f32<KIND>(j, c + 1, id, k0, k1);
+    const float p3 = node_f32<KIND>(j, c + 2, id, k0, k1);
+    const float sg = (KIND == kRF) ? (float)strength : -(float)strength;
+    out[i] = (double)(sg * spline_f32<KIND>(p0, p1, p2, p3, r));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+#define QEW_KIND_DISPATCH(kind, KERNEL, ...)                      \
+  do {                                                            \
+    if ((kind) == kRF)                                            \
+      hipLaunchKernelGGL(KERNEL<kRF>, __VA_ARGS__);               \
+    else                                                          \
+      hipLaunchKernelGGL(KERNEL<kRB>, __VA_ARGS__);               \
+  } while (0)
+
+hipError_t launch_init_plain(const Tables& t, double* u, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_plain, dim3(t.n_mt), dim3(kBlock), 0, st, t, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_split(const Tables& t, SplitBuf b, const Phys& ph, int kind, bool nodes,
+                             hipStream_t st) {
+  QEW_KIND_DISPATCH(kind, k_init_split, dim3(t.n_mt), dim3(kBlock), 0, st, t, b, ph, nodes ? 1 : 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_nodes(const Tables& t, SplitBuf b, const Phys& ph, int kind,
+                                hipStream_t st) {
+  QEW_KIND_DISPATCH(kind, k_init_split, dim3(t.n_mt), dim3(kBlock), 0, st, t, b, ph, 1, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_plain(const Tables& t, const double* uin, double* uout, const Phys& ph,
+                             int kind, hipStream_t st) {
+  QEW_KIND_DISPATCH(kind, k_step_plain, dim3(t.n_mt), dim3(kBlock), 0, st, t, uin, uout, ph);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_split1(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
+                              hipStream_t st) {
+  QEW_KIND_DISPATCH(kind, k_step_split1, dim3(t.n_mt), dim3(kBlock), 0, st, t, in, out, ph);
+  return hipGetLastError();
+}
+
+template <int KIND, int P>
+static const void* fused_ptr() {
+  return reinterpret_cast<const void*>(&k_step_fused<KIND, P>);
+}
+
+int fused_max_grid(int tile) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* fn = tile == 512 ? fused_ptr<kRF, 8>() : tile == 1024 ? fused_ptr<kRF, 16>() : fused_ptr<kRF, 32>();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess) return 0;
+  if (per_cu < 1) per_cu = 1;
+  return cus * per_cu;
+}
+
+hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
+                             int tile, int halo, int nsub, int grid, hipStream_t st) {
+  const dim3 g(grid), b(kBlock);
+  if (kind == kRF) {
+    if (tile == 512) hipLaunchKernelGGL((k_step_fused<kRF, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRF, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else hipLaunchKernelGGL((k_step_fused<kRF, 32>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  } else {
+    if (tile == 512) hipLaunchKernelGGL((k_step_fused<kRB, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRB, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else hipLaunchKernelGGL((k_step_fused<kRB, 32>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_meas_plain(const Tables& t, const double* u, const Phys& ph, int kind,
+                             Partial* part, hipStream_t st) {
+  QEW_KIND_DISPATCH(kind, k_meas_plain, dim3(t.n_mt), dim3(kBlock), 0, st, t, u, ph, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_meas_split(const Tables& t, SplitBuf b, const Phys& ph, int kind, Partial* part,
+                             hipStream_t st) {
+  QEW_KIND_DISPATCH(kind, k_meas_split, dim3(t.n_mt), dim3(kBlock), 0, st, t, b, ph, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_meas_final(const Tables& t, int n_samples, const Partial* part, int meas_index,
+                             int n_meas, double* series, hipStream_t st) {
+  hipLaunchKernelGGL(k_meas_final, dim3(n_samples), dim3(kBlock), 0, st, t, part, meas_index, n_meas,
+                     series);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_fill(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
+                              int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_philox_fill, dim3((uint32_t)blocks), dim3(kBlock), 0, st,
+                     reinterpret_cast<const uint4*>(ctr), k0, k1, reinterpret_cast<uint4*>(out), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int precision,
+                             const uint32_t* did, const int32_t* j, const int32_t* cell,
+                             const double* frac, double* out, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  QEW_KIND_DISPATCH(kind, k_force_eval, dim3((uint32_t)blocks), dim3(kBlock), 0, st, strength, k0, k1,
+                    precision, did, j, cell, frac, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace qew

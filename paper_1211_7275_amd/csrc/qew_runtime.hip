@@ -1,0 +1,783 @@
+// qew_runtime.hip -- host runtime and C ABI of libqew (declared in include/qew.h).
+//
+// A plan holds the validated problem, the per-sample offsets of the state
+// buffers, two tile work lists (measurement / one-step tiles of fixed size,
+// and fused wave tiles whose valid width depends on the blocking depth k),
+// and the layout of the caller's workspace.  qew_run walks the measurement
+// steps: at each one it reduces Eqs. (3)-(5) of the state, and between them
+// it advances the chains by Euler steps (Eq. (1), Sec. III B), one or k steps
+// per launch, replaying captured hipGraphs of 16 launches where it can.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qew.h"
+#include "qew_internal.hpp"
+
+using namespace qew;
+
+namespace {
+
+thread_local std::string g_err;
+
+qew_status fail(qew_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define QEW_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(QEW_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr int64_t kMaxL = int64_t(1) << 30;
+constexpr int kGraphLaunches = 16;
+constexpr int kTuneTiles[3] = {512, 1024, 2048};
+constexpr int kTuneK[3] = {8, 16, 32};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len;
+  size_t tables_end;
+  size_t part, series, stA0, stA1, stB0, stB1, ndA, ndB;
+  size_t total;
+};
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  int key_k = -1, key_tile = -1, key_grid = -1;
+};
+
+}  // namespace
+
+struct qew_plan_s {
+  // problem
+  int32_t S = 0, kind = 0, precision = 0, path = 0, k_req = 0, tile_req = 0, flags = 0;
+  double c = 0, dt = 0, strength = 0;
+  uint64_t seed = 0;
+  int64_t n_steps = 0;
+  std::vector<int64_t> L, meas;
+  std::vector<double> f;
+  std::vector<uint32_t> did;
+  // derived
+  std::vector<int64_t> off;
+  int64_t padded = 0, total_sites = 0;
+  std::vector<int32_t> mt_s, mt_p0, mt_len, mt_first;
+  std::vector<int32_t> ft_s, ft_p0, ft_len;
+  int32_t ft_capacity = 0;
+  int32_t k = 1, tile = 0, autotuned = 0;
+  Layout lay{};
+  // run state
+  int64_t cur_step = 0;
+  int cur_buf = 0;
+  void* state_ws = nullptr;
+  bool nodes_valid = false;
+  int fused_grid = 0;
+  hipStream_t cap_stream = nullptr;
+  GraphCache graph;
+  qew_run_stats stats{};
+};
+
+namespace {
+
+bool fused(const qew_plan_t* p) { return p->path == QEW_FUSED; }
+
+void build_fused_tiles(qew_plan_t* p, int tile, int k) {
+  p->ft_s.clear();
+  p->ft_p0.clear();
+  p->ft_len.clear();
+  const int64_t V = tile - 2 * k;
+  for (int32_t s = 0; s < p->S; ++s) {
+    const int64_t L = p->L[s];
+    for (int64_t p0 = 0; p0 < L; p0 += V) {
+      p->ft_s.push_back(s);
+      p->ft_p0.push_back((int32_t)p0);
+      p->ft_len.push_back((int32_t)std::min<int64_t>(V, L - p0));
+    }
+  }
+  p->k = k;
+  p->tile = tile;
+}
+
+int64_t fused_tile_count(const qew_plan_t* p, int tile, int k) {
+  const int64_t V = tile - 2 * k;
+  int64_t n = 0;
+  for (int64_t L : p->L) n += (L + V - 1) / V;
+  return n;
+}
+
+void compute_layout(qew_plan_t* p) {
+  Layout& l = p->lay;
+  const size_t S = (size_t)p->S;
+  const size_t nmt = p->mt_s.size();
+  const size_t nft = (size_t)p->ft_capacity;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  l.off = take(S * 8);
+  l.L = take(S * 4);
+  l.f = take(S * 8);
+  l.f32 = take(S * 4);
+  l.did = take(S * 4);
+  l.mt_s = take(nmt * 4);
+  l.mt_p0 = take(nmt * 4);
+  l.mt_len = take(nmt * 4);
+  l.mt_first = take((S + 1) * 4);
+  l.ft_s = take(nft * 4);
+  l.ft_p0 = take(nft * 4);
+  l.ft_len = take(nft * 4);
+  l.tables_end = o;
+  l.part = take(nmt * sizeof(Partial));
+  l.series = take(S * std::max<size_t>(p->meas.size(), 1) * 3 * 8);
+  const size_t n = (size_t)p->padded;
+  if (p->precision == QEW_FP64_PLAIN) {
+    l.stA0 = take(n * 8);
+    l.stA1 = 0;
+    l.stB0 = take(n * 8);
+    l.stB1 = 0;
+  } else {
+    l.stA0 = take(n * 4);
+    l.stA1 = take(n * 4);
+    l.stB0 = take(n * 4);
+    l.stB1 = take(n * 4);
+  }
+  if (fused(p)) {
+    l.ndA = take(n * 16);
+    l.ndB = take(n * 16);
+  } else {
+    l.ndA = l.ndB = 0;
+  }
+  l.total = o;
+}
+
+Tables tables_of(const qew_plan_t* p, void* ws) {
+  char* b = static_cast<char*>(ws);
+  const Layout& l = p->lay;
+  Tables t;
+  t.off = reinterpret_cast<const int64_t*>(b + l.off);
+  t.L = reinterpret_cast<const int32_t*>(b + l.L);
+  t.f = reinterpret_cast<const double*>(b + l.f);
+  t.f32 = reinterpret_cast<const float*>(b + l.f32);
+  t.did = reinterpret_cast<const uint32_t*>(b + l.did);
+  t.mt_s = reinterpret_cast<const int32_t*>(b + l.mt_s);
+  t.mt_p0 = reinterpret_cast<const int32_t*>(b + l.mt_p0);
+  t.mt_len = reinterpret_cast<const int32_t*>(b + l.mt_len);
+  t.mt_first = reinterpret_cast<const int32_t*>(b + l.mt_first);
+  t.ft_s = reinterpret_cast<const int32_t*>(b + l.ft_s);
+  t.ft_p0 = reinterpret_cast<const int32_t*>(b + l.ft_p0);
+  t.ft_len = reinterpret_cast<const int32_t*>(b + l.ft_len);
+  t.n_mt = (int32_t)p->mt_s.size();
+  t.n_ft = (int32_t)p->ft_s.size();
+  return t;
+}
+
+Phys phys_of(const qew_plan_t* p) {
+  Phys ph;
+  ph.c = p->c;
+  ph.dt = p->dt;
+  ph.strength = p->strength;
+  ph.cf = (float)p->c;
+  ph.dtf = (float)p->dt;
+  ph.sgn_strf = p->kind == QEW_RF_CR_UNIFORM ? (float)p->strength : -(float)p->strength;
+  ph.k0 = (uint32_t)(p->seed & 0xffffffffu);
+  ph.k1 = (uint32_t)(p->seed >> 32);
+  return ph;
+}
+
+double* plain_buf(const qew_plan_t* p, void* ws, int which) {
+  return reinterpret_cast<double*>(static_cast<char*>(ws) + (which ? p->lay.stB0 : p->lay.stA0));
+}
+
+SplitBuf split_buf(const qew_plan_t* p, void* ws, int which) {
+  char* b = static_cast<char*>(ws);
+  const Layout& l = p->lay;
+  SplitBuf s;
+  s.cell = reinterpret_cast<int32_t*>(b + (which ? l.stB0 : l.stA0));
+  s.frac = reinterpret_cast<float*>(b + (which ? l.stB1 : l.stA1));
+  s.nodes = fused(p) ? reinterpret_cast<float4*>(b + (which ? l.ndB : l.ndA)) : nullptr;
+  return s;
+}
+
+// Host image of the table region (offsets as laid out in the workspace).
+std::vector<char> table_image(const qew_plan_t* p) {
+  const Layout& l = p->lay;
+  std::vector<char> img(l.tables_end, 0);
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(img.data() + at, src, bytes);
+  };
+  std::vector<int32_t> L32(p->S);
+  std::vector<float> f32(p->S);
+  for (int s = 0; s < p->S; ++s) {
+    L32[s] = (int32_t)p->L[s];
+    f32[s] = (float)p->f[s];
+  }
+  put(l.off, p->off.data(), p->S * 8);
+  put(l.L, L32.data(), p->S * 4);
+  put(l.f, p->f.data(), p->S * 8);
+  put(l.f32, f32.data(), p->S * 4);
+  put(l.did, p->did.data(), p->S * 4);
+  put(l.mt_s, p->mt_s.data(), p->mt_s.size() * 4);
+  put(l.mt_p0, p->mt_p0.data(), p->mt_p0.size() * 4);
+  put(l.mt_len, p->mt_len.data(), p->mt_len.size() * 4);
+  put(l.mt_first, p->mt_first.data(), p->mt_first.size() * 4);
+  put(l.ft_s, p->ft_s.data(), p->ft_s.size() * 4);
+  put(l.ft_p0, p->ft_p0.data(), p->ft_p0.size() * 4);
+  put(l.ft_len, p->ft_len.data(), p->ft_len.size() * 4);
+  return img;
+}
+
+qew_status upload_tables(qew_plan_t* p, void* ws, hipStream_t st) {
+  std::vector<char> img = table_image(p);
+  QEW_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
+  QEW_HIP(hipStreamSynchronize(st));
+  return QEW_OK;
+}
+
+qew_status init_state(qew_plan_t* p, void* ws, hipStream_t st) {
+  const Tables t = tables_of(p, ws);
+  if (p->precision == QEW_FP64_PLAIN) {
+    QEW_HIP(launch_init_plain(t, plain_buf(p, ws, 0), st));
+  } else {
+    QEW_HIP(launch_init_split(t, split_buf(p, ws, 0), phys_of(p), p->kind, fused(p), st));
+  }
+  p->cur_buf = 0;
+  p->cur_step = 0;
+  p->state_ws = ws;
+  p->nodes_valid = true;
+  return QEW_OK;
+}
+
+// One launch of the stepping kernel: nsub Euler steps from buffer `from`.
+hipError_t step_launch(const qew_plan_t* p, void* ws, int from, int nsub, hipStream_t st) {
+  const Tables t = tables_of(p, ws);
+  const Phys ph = phys_of(p);
+  if (p->precision == QEW_FP64_PLAIN)
+    return launch_step_plain(t, plain_buf(p, ws, from), plain_buf(p, ws, from ^ 1), ph, p->kind, st);
+  if (!fused(p))
+    return launch_step_split1(t, split_buf(p, ws, from), split_buf(p, ws, from ^ 1), ph, p->kind, st);
+  return launch_step_fused(t, split_buf(p, ws, from), split_buf(p, ws, from ^ 1), ph, p->kind, p->tile,
+                           p->k, nsub, p->fused_grid, st);
+}
+
+qew_status ensure_fused_grid(qew_plan_t* p) {
+  if (!fused(p)) return QEW_OK;
+  const int maxg = fused_max_grid(p->tile);
+  if (maxg <= 0) return fail(QEW_EDEVICE, "could not query occupancy of the fused kernel");
+  const int need = (int)((p->ft_s.size() + (kBlock / 64) - 1) / (kBlock / 64));
+  p->fused_grid = std::max(1, std::min(need, maxg));
+  return QEW_OK;
+}
+
+void drop_graph(qew_plan_t* p) {
+  if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
+  p->graph = GraphCache{};
+}
+
+// Graph of kGraphLaunches full launches starting (and ending) at buffer 0.
+qew_status ensure_graph(qew_plan_t* p, void* ws) {
+  GraphCache& g = p->graph;
+  if (g.exec && g.ws == ws && g.key_k == p->k && g.key_tile == p->tile && g.key_grid == p->fused_grid)
+    return QEW_OK;
+  drop_graph(p);
+  if (!p->cap_stream) QEW_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  QEW_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < kGraphLaunches && le == hipSuccess; ++i)
+    le = step_launch(p, ws, i & 1, p->k, p->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(p->cap_stream, &graph);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(QEW_EDEVICE, "graph capture failed: %s",
+                hipGetErrorString(le != hipSuccess ? le : ee));
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(QEW_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+  g.exec = exec;
+  g.ws = ws;
+  g.key_k = p->k;
+  g.key_tile = p->tile;
+  g.key_grid = p->fused_grid;
+  return QEW_OK;
+}
+
+// Advance the state by n Euler steps (buffer parity tracked in the plan).
+qew_status advance(qew_plan_t* p, void* ws, int64_t n, hipStream_t st) {
+  const int kk = p->k;
+  int64_t blocks = n / kk;
+  const int rem = (int)(n % kk);
+  const bool use_graph = !(p->flags & QEW_FLAG_NO_GRAPH);
+  if (use_graph && blocks >= kGraphLaunches + (p->cur_buf ? 1 : 0)) {
+    if (p->cur_buf) {
+      QEW_HIP(step_launch(p, ws, p->cur_buf, kk, st));
+      p->cur_buf ^= 1;
+      p->stats.step_launches++;
+      --blocks;
+    }
+    qew_status rc = ensure_graph(p, ws);
+    if (rc != QEW_OK) return rc;
+    while (blocks >= kGraphLaunches) {
+      QEW_HIP(hipGraphLaunch(p->graph.exec, st));
+      blocks -= kGraphLaunches;
+      p->stats.step_launches += kGraphLaunches;
+      p->stats.graph_launches++;
+    }
+  }
+  for (; blocks > 0; --blocks) {
+    QEW_HIP(step_launch(p, ws, p->cur_buf, kk, st));
+    p->cur_buf ^= 1;
+    p->stats.step_launches++;
+  }
+  if (rem) {
+    QEW_HIP(step_launch(p, ws, p->cur_buf, rem, st));
+    p->cur_buf ^= 1;
+    p->stats.step_launches++;
+  }
+  return QEW_OK;
+}
+
+qew_status measure(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
+  const Tables t = tables_of(p, ws);
+  const Phys ph = phys_of(p);
+  Partial* part = reinterpret_cast<Partial*>(static_cast<char*>(ws) + p->lay.part);
+  double* series = reinterpret_cast<double*>(static_cast<char*>(ws) + p->lay.series);
+  if (p->precision == QEW_FP64_PLAIN)
+    QEW_HIP(launch_meas_plain(t, plain_buf(p, ws, p->cur_buf), ph, p->kind, part, st));
+  else
+    QEW_HIP(launch_meas_split(t, split_buf(p, ws, p->cur_buf), ph, p->kind, part, st));
+  QEW_HIP(launch_meas_final(t, p->S, part, mi, (int)p->meas.size(), series, st));
+  p->stats.meas_launches++;
+  return QEW_OK;
+}
+
+qew_status check_ws(const qew_plan_t* p, const void* ws, size_t bytes) {
+  if (!p) return fail(QEW_EINVAL, "plan is NULL");
+  if (!ws) return fail(QEW_EINVAL, "workspace pointer is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(QEW_EINVAL, "workspace is not 256-byte aligned");
+  if (bytes < p->lay.total)
+    return fail(QEW_ENOMEM, "workspace holds %zu bytes, the plan needs %zu", bytes, p->lay.total);
+  return QEW_OK;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* qew_last_error(void) { return g_err.c_str(); }
+
+qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
+  g_err.clear();
+  if (!out) return fail(QEW_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pr) return fail(QEW_EINVAL, "problem is NULL");
+  if (pr->n_samples < 1) return fail(QEW_EINVAL, "n_samples must be >= 1 (got %d)", pr->n_samples);
+  if (!pr->L || !pr->f || !pr->disorder_id) return fail(QEW_EINVAL, "L, f and disorder_id must be non-NULL");
+  if (pr->kind != QEW_RF_CR_UNIFORM && pr->kind != QEW_RB_CR_GAUSS) return fail(QEW_EINVAL, "unknown disorder kind %d", pr->kind);
+  if (!(std::isfinite(pr->c) && pr->c > 0)) return fail(QEW_EINVAL, "c must be finite and > 0");
+  if (!(std::isfinite(pr->dt) && pr->dt > 0)) return fail(QEW_EINVAL, "dt must be finite and > 0");
+  if (!(pr->c * pr->dt <= 0.5)) return fail(QEW_EINVAL, "c*dt = %g exceeds 1/2 (explicit Euler is unstable)", pr->c * pr->dt);
+  if (!(std::isfinite(pr->strength) && pr->strength >= 0)) return fail(QEW_EINVAL, "strength must be finite and >= 0");
+  if (pr->n_steps < 0 || pr->n_steps > (int64_t(1) << 53)) return fail(QEW_EINVAL, "n_steps out of range");
+  if (pr->n_meas < 0) return fail(QEW_EINVAL, "n_meas must be >= 0");
+  if (pr->n_meas > 0 && !pr->meas_steps) return fail(QEW_EINVAL, "meas_steps is NULL");
+  for (int32_t i = 0; i < pr->n_meas; ++i) {
+    const int64_t m = pr->meas_steps[i];
+    if (m < 0 || m > pr->n_steps) return fail(QEW_EINVAL, "meas_steps[%d] = %lld outside [0, n_steps]", i, (long long)m);
+    if (i > 0 && m <= pr->meas_steps[i - 1]) return fail(QEW_EINVAL, "meas_steps must be strictly increasing (index %d)", i);
+  }
+  if (pr->precision != QEW_FP64_PLAIN && pr->precision != QEW_FP32_SPLIT) return fail(QEW_EINVAL, "unknown precision %d", pr->precision);
+  if (pr->path != QEW_ONE_STEP && pr->path != QEW_FUSED) return fail(QEW_EINVAL, "unknown path %d", pr->path);
+  if (pr->path == QEW_FUSED && pr->precision != QEW_FP32_SPLIT)
+    return fail(QEW_EUNSUPPORTED, "the fused path runs in FP32 split precision only");
+  if (pr->k < 0 || pr->k > kMaxHalo) return fail(QEW_EINVAL, "k must be in [0, %d]", kMaxHalo);
+  if (pr->tile != 0 && pr->tile != 512 && pr->tile != 1024 && pr->tile != 2048)
+    return fail(QEW_EINVAL, "tile must be 0, 512, 1024 or 2048");
+  if (pr->k > 0 && pr->tile > 0 && 4 * pr->k > pr->tile) return fail(QEW_EINVAL, "need 4*k <= tile");
+  if (pr->flags & ~(QEW_FLAG_NO_GRAPH | QEW_FLAG_TIMING)) return fail(QEW_EINVAL, "unknown flag bits");
+  for (int32_t s = 0; s < pr->n_samples; ++s) {
+    if (pr->L[s] < 3 || pr->L[s] > kMaxL) return fail(QEW_EINVAL, "L[%d] = %lld outside [3, 2^30]", s, (long long)pr->L[s]);
+    if (!std::isfinite(pr->f[s])) return fail(QEW_EINVAL, "f[%d] is not finite", s);
+  }
+
+  qew_plan_t* p = new (std::nothrow) qew_plan_t();
+  if (!p) return fail(QEW_EINVAL, "out of host memory");
+  p->S = pr->n_samples;
+  p->kind = pr->kind;
+  p->precision = pr->precision;
+  p->path = pr->path;
+  p->k_req = pr->k;
+  p->tile_req = pr->tile;
+  p->flags = pr->flags;
+  p->c = pr->c;
+  p->dt = pr->dt;
+  p->strength = pr->strength;
+  p->seed = pr->seed;
+  p->n_steps = pr->n_steps;
+  p->L.assign(pr->L, pr->L + p->S);
+  p->f.assign(pr->f, pr->f + p->S);
+  p->did.assign(pr->disorder_id, pr->disorder_id + p->S);
+  if (pr->n_meas > 0) p->meas.assign(pr->meas_steps, pr->meas_steps + pr->n_meas);
+
+  int64_t o = 0;
+  p->off.resize(p->S);
+  p->mt_first.push_back(0);
+  for (int32_t s = 0; s < p->S; ++s) {
+    p->off[s] = o;
+    o += (p->L[s] + 63) / 64 * 64;
+    p->total_sites += p->L[s];
+    for (int64_t p0 = 0; p0 < p->L[s]; p0 += kMeasTile) {
+      p->mt_s.push_back(s);
+      p->mt_p0.push_back((int32_t)p0);
+      p->mt_len.push_back((int32_t)std::min<int64_t>(kMeasTile, p->L[s] - p0));
+    }
+    p->mt_first.push_back((int32_t)p->mt_s.size());
+  }
+  p->padded = o;
+  if (p->mt_s.size() > (size_t)INT32_MAX / 2) {
+    delete p;
+    return fail(QEW_EINVAL, "too many sites");
+  }
+
+  if (fused(p)) {
+    int64_t cap = 0;
+    for (int tile : kTuneTiles) {
+      if (p->tile_req && tile != p->tile_req) continue;
+      for (int k : kTuneK) {
+        const int kk = p->k_req ? p->k_req : k;
+        if (4 * kk > tile) continue;
+        cap = std::max(cap, fused_tile_count(p, tile, kk));
+      }
+    }
+    if (p->k_req && p->tile_req) cap = fused_tile_count(p, p->tile_req, p->k_req);
+    if (cap == 0) {
+      delete p;
+      return fail(QEW_EINVAL, "no fused geometry satisfies 4*k <= tile");
+    }
+    if (cap > INT32_MAX / 2) {
+      delete p;
+      return fail(QEW_EINVAL, "too many fused tiles");
+    }
+    p->ft_capacity = (int32_t)cap;
+    const int tile0 = p->tile_req ? p->tile_req : 1024;
+    int k0 = p->k_req ? p->k_req : 16;
+    if (4 * k0 > tile0) k0 = tile0 / 4;
+    build_fused_tiles(p, tile0, k0);
+  } else {
+    p->k = 1;
+    p->tile = 0;
+  }
+  compute_layout(p);
+  *out = p;
+  return QEW_OK;
+}
+
+size_t qew_workspace_bytes(const qew_plan_t* p) { return p ? p->lay.total : 0; }
+
+qew_status qew_plan_info_get(const qew_plan_t* p, qew_plan_info* info) {
+  if (!p || !info) return fail(QEW_EINVAL, "plan and info must be non-NULL");
+  info->total_sites = p->total_sites;
+  info->padded_sites = p->padded;
+  info->n_tiles = fused(p) ? (int32_t)p->ft_s.size() : (int32_t)p->mt_s.size();
+  info->n_meas_tiles = (int32_t)p->mt_s.size();
+  info->k = p->k;
+  info->tile = p->tile;
+  info->autotuned = p->autotuned;
+  info->pad_ = 0;
+  info->cur_step = p->cur_step;
+  return QEW_OK;
+}
+
+qew_status qew_run_stats_get(const qew_plan_t* p, qew_run_stats* st) {
+  if (!p || !st) return fail(QEW_EINVAL, "plan and stats must be non-NULL");
+  *st = p->stats;
+  return QEW_OK;
+}
+
+qew_status qew_autotune(qew_plan_t* p, void* ws, size_t bytes, void* stream) {
+  qew_status rc = check_ws(p, ws, bytes);
+  if (rc != QEW_OK) return rc;
+  if (!fused(p)) return QEW_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QEW_HIP(hipEventCreate(&e0));
+  QEW_HIP(hipEventCreate(&e1));
+  double best = -1.0;
+  int best_tile = p->tile, best_k = p->k;
+  for (int tile : kTuneTiles) {
+    if (p->tile_req && tile != p->tile_req) continue;
+    for (int kc : kTuneK) {
+      const int k = p->k_req ? p->k_req : kc;
+      if (4 * k > tile) continue;
+      if (p->k_req && kc != kTuneK[0]) continue;  // a fixed k is timed once per tile
+      build_fused_tiles(p, tile, k);
+      if ((rc = upload_tables(p, ws, st)) != QEW_OK) break;
+      if ((rc = init_state(p, ws, st)) != QEW_OK) break;
+      if ((rc = ensure_fused_grid(p)) != QEW_OK) break;
+      const int steps = std::max(2 * k, 64);
+      const int launches = steps / k;
+      hipError_t he = step_launch(p, ws, 0, k, st);  // warm-up
+      if (he == hipSuccess) he = hipEventRecord(e0, st);
+      for (int i = 0; i < launches && he == hipSuccess; ++i) he = step_launch(p, ws, (i + 1) & 1, k, st);
+      if (he == hipSuccess) he = hipEventRecord(e1, st);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        rc = fail(QEW_EDEVICE, "autotune run failed: %s", hipGetErrorString(he));
+        break;
+      }
+      const double rate = (double)p->total_sites * launches * k / (ms > 0 ? ms : 1e-9);
+      if (rate > best) {
+        best = rate;
+        best_tile = tile;
+        best_k = k;
+      }
+    }
+    if (rc != QEW_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != QEW_OK) return rc;
+  build_fused_tiles(p, best_tile, best_k);
+  p->autotuned = 1;
+  p->state_ws = nullptr;  // the state was overwritten
+  drop_graph(p);
+  return QEW_OK;
+}
+
+qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t resume, double* h_v,
+                   double* h_w2, double* h_ubar) {
+  g_err.clear();
+  qew_status rc = check_ws(p, ws, bytes);
+  if (rc != QEW_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (resume && (p->state_ws != ws)) return fail(QEW_EINVAL, "resume: this workspace holds no state of this plan");
+  if (resume && p->cur_step > p->n_steps) return fail(QEW_EINVAL, "resume: state step beyond n_steps");
+  if (fused(p) && (p->k_req == 0 || p->tile_req == 0) && !p->autotuned) {
+    if (resume) return fail(QEW_EINVAL, "resume: run qew_autotune before writing the state");
+    if ((rc = qew_autotune(p, ws, bytes, stream)) != QEW_OK) return rc;
+  }
+  p->stats = qew_run_stats{};
+  if ((rc = upload_tables(p, ws, st)) != QEW_OK) return rc;
+  if ((rc = ensure_fused_grid(p)) != QEW_OK) return rc;
+  if (!resume) {
+    if ((rc = init_state(p, ws, st)) != QEW_OK) return rc;
+  } else if (fused(p) && !p->nodes_valid) {
+    QEW_HIP(launch_refresh_nodes(tables_of(p, ws), split_buf(p, ws, p->cur_buf), phys_of(p), p->kind, st));
+    p->nodes_valid = true;
+  }
+  const bool timing = (p->flags & QEW_FLAG_TIMING) != 0;
+  std::vector<EventPair> step_ev, meas_ev;
+  EventPair whole;
+  auto mk = [&](EventPair& e) -> hipError_t {
+    hipError_t r = hipEventCreate(&e.a);
+    if (r == hipSuccess) r = hipEventCreate(&e.b);
+    return r;
+  };
+  auto cleanup = [&]() {
+    for (auto& e : step_ev) { if (e.a) (void)hipEventDestroy(e.a); if (e.b) (void)hipEventDestroy(e.b); }
+    for (auto& e : meas_ev) { if (e.a) (void)hipEventDestroy(e.a); if (e.b) (void)hipEventDestroy(e.b); }
+    if (whole.a) (void)hipEventDestroy(whole.a);
+    if (whole.b) (void)hipEventDestroy(whole.b);
+  };
+  const int64_t step0 = p->cur_step;
+  const int n_meas = (int)p->meas.size();
+  int mi = (int)(std::lower_bound(p->meas.begin(), p->meas.end(), step0) - p->meas.begin());
+  const int mi0 = mi;
+  hipError_t he = hipSuccess;
+  if (timing) {
+    he = mk(whole);
+    if (he == hipSuccess) he = hipEventRecord(whole.a, st);
+  }
+  int64_t m = step0;
+  while (he == hipSuccess && rc == QEW_OK) {
+    if (mi < n_meas && p->meas[mi] == m) {
+      if (timing) {
+        meas_ev.emplace_back();
+        if ((he = mk(meas_ev.back())) != hipSuccess) break;
+        if ((he = hipEventRecord(meas_ev.back().a, st)) != hipSuccess) break;
+      }
+      if ((rc = measure(p, ws, mi, st)) != QEW_OK) break;
+      if (timing && (he = hipEventRecord(meas_ev.back().b, st)) != hipSuccess) break;
+      ++mi;
+    }
+    if (m >= p->n_steps) break;
+    const int64_t stop = (mi < n_meas) ? p->meas[mi] : p->n_steps;
+    if (timing) {
+      step_ev.emplace_back();
+      if ((he = mk(step_ev.back())) != hipSuccess) break;
+      if ((he = hipEventRecord(step_ev.back().a, st)) != hipSuccess) break;
+    }
+    if ((rc = advance(p, ws, stop - m, st)) != QEW_OK) break;
+    if (timing && (he = hipEventRecord(step_ev.back().b, st)) != hipSuccess) break;
+    m = stop;
+  }
+  if (he == hipSuccess && rc == QEW_OK && timing) he = hipEventRecord(whole.b, st);
+  if (he != hipSuccess && rc == QEW_OK) rc = fail(QEW_EDEVICE, "event/launch failed: %s", hipGetErrorString(he));
+  if (rc != QEW_OK) {
+    (void)hipStreamSynchronize(st);
+    cleanup();
+    p->state_ws = nullptr;
+    return rc;
+  }
+  std::vector<double> series;
+  if (n_meas > mi0) {
+    series.resize((size_t)p->S * n_meas * 3);
+    he = hipMemcpyAsync(series.data(), static_cast<char*>(ws) + p->lay.series, series.size() * 8,
+                        hipMemcpyDeviceToHost, st);
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) {
+    cleanup();
+    p->state_ws = nullptr;
+    return fail(QEW_EDEVICE, "run failed: %s", hipGetErrorString(he));
+  }
+  for (int s = 0; s < p->S && n_meas > mi0; ++s) {
+    for (int i = mi0; i < n_meas; ++i) {
+      const double* x = &series[((size_t)s * n_meas + i) * 3];
+      if (h_v) h_v[(size_t)s * n_meas + i] = x[0];
+      if (h_ubar) h_ubar[(size_t)s * n_meas + i] = x[1];
+      if (h_w2) h_w2[(size_t)s * n_meas + i] = x[2];
+    }
+  }
+  if (timing) {
+    float ms = 0.0f;
+    for (auto& e : step_ev)
+      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) p->stats.step_ms += ms;
+    for (auto& e : meas_ev)
+      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) p->stats.meas_ms += ms;
+    if (hipEventElapsedTime(&ms, whole.a, whole.b) == hipSuccess) p->stats.total_ms = ms;
+  }
+  cleanup();
+  p->stats.site_updates = p->total_sites * (p->n_steps - step0);
+  p->cur_step = p->n_steps;
+  p->state_ws = ws;
+  p->nodes_valid = true;
+  return QEW_OK;
+}
+
+qew_status qew_read_state(const qew_plan_t* p, const void* ws, void* stream, int32_t s, double* h_u,
+                          int64_t* h_step) {
+  g_err.clear();
+  if (!p || !ws || !h_u) return fail(QEW_EINVAL, "plan, workspace and h_u must be non-NULL");
+  if (s < 0 || s >= p->S) return fail(QEW_EINVAL, "sample %d out of range", s);
+  if (p->state_ws != ws) return fail(QEW_EINVAL, "this workspace holds no state of this plan");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t L = p->L[s];
+  void* w = const_cast<void*>(ws);
+  if (p->precision == QEW_FP64_PLAIN) {
+    QEW_HIP(hipMemcpyAsync(h_u, plain_buf(p, w, p->cur_buf) + p->off[s], L * 8, hipMemcpyDeviceToHost, st));
+    QEW_HIP(hipStreamSynchronize(st));
+  } else {
+    std::vector<int32_t> c(L);
+    std::vector<float> r(L);
+    const SplitBuf b = split_buf(p, w, p->cur_buf);
+    QEW_HIP(hipMemcpyAsync(c.data(), b.cell + p->off[s], L * 4, hipMemcpyDeviceToHost, st));
+    QEW_HIP(hipMemcpyAsync(r.data(), b.frac + p->off[s], L * 4, hipMemcpyDeviceToHost, st));
+    QEW_HIP(hipStreamSynchronize(st));
+    for (int64_t j = 0; j < L; ++j) h_u[j] = (double)c[j] + (double)r[j];
+  }
+  if (h_step) *h_step = p->cur_step;
+  return QEW_OK;
+}
+
+qew_status qew_write_state(qew_plan_t* p, void* ws, void* stream, int32_t s, const double* h_u,
+                           int64_t step) {
+  g_err.clear();
+  if (!p || !ws || !h_u) return fail(QEW_EINVAL, "plan, workspace and h_u must be non-NULL");
+  if (s < 0 || s >= p->S) return fail(QEW_EINVAL, "sample %d out of range", s);
+  if (step < 0 || step > p->n_steps) return fail(QEW_EINVAL, "step outside [0, n_steps]");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(QEW_EINVAL, "workspace is not 256-byte aligned");
+  const int64_t L = p->L[s];
+  for (int64_t j = 0; j < L; ++j)
+    if (!std::isfinite(h_u[j]) || std::fabs(h_u[j]) > 1e9) return fail(QEW_EINVAL, "h_u[%lld] not finite or beyond 1e9", (long long)j);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->state_ws != ws) p->cur_buf = 0;
+  if (p->precision == QEW_FP64_PLAIN) {
+    QEW_HIP(hipMemcpyAsync(plain_buf(p, ws, p->cur_buf) + p->off[s], h_u, L * 8, hipMemcpyHostToDevice, st));
+    QEW_HIP(hipStreamSynchronize(st));
+  } else {
+    std::vector<int32_t> c(L);
+    std::vector<float> r(L);
+    for (int64_t j = 0; j < L; ++j) {
+      const double fl = std::floor(h_u[j]);
+      float fr = (float)(h_u[j] - fl);
+      int32_t cc = (int32_t)fl;
+      if (fr >= 1.0f) {
+        fr = 0.0f;
+        cc += 1;
+      }
+      c[j] = cc;
+      r[j] = fr;
+    }
+    const SplitBuf b = split_buf(p, ws, p->cur_buf);
+    QEW_HIP(hipMemcpyAsync(b.cell + p->off[s], c.data(), L * 4, hipMemcpyHostToDevice, st));
+    QEW_HIP(hipMemcpyAsync(b.frac + p->off[s], r.data(), L * 4, hipMemcpyHostToDevice, st));
+    QEW_HIP(hipStreamSynchronize(st));
+  }
+  p->cur_step = step;
+  p->state_ws = ws;
+  p->nodes_valid = false;
+  return QEW_OK;
+}
+
+qew_status qew_debug_philox_fill(const uint32_t* d_ctr, uint64_t seed, uint32_t* d_out, int64_t N,
+                                 void* stream) {
+  g_err.clear();
+  if (N < 0) return fail(QEW_EINVAL, "N < 0");
+  if (N > 0 && (!d_ctr || !d_out)) return fail(QEW_EINVAL, "NULL device pointer");
+  if (N > (int64_t(1) << 31) * 256) return fail(QEW_EINVAL, "N too large");
+  QEW_HIP(launch_philox_fill(d_ctr, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), d_out, N,
+                             static_cast<hipStream_t>(stream)));
+  return QEW_OK;
+}
+
+qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, int32_t precision,
+                                const uint32_t* d_did, const int32_t* d_j, const int32_t* d_cell,
+                                const double* d_frac, double* d_out, int64_t N, void* stream) {
+  g_err.clear();
+  if (kind != QEW_RF_CR_UNIFORM && kind != QEW_RB_CR_GAUSS) return fail(QEW_EINVAL, "unknown kind");
+  if (precision != QEW_FP64_PLAIN && precision != QEW_FP32_SPLIT) return fail(QEW_EINVAL, "unknown precision");
+  if (!(std::isfinite(strength) && strength >= 0)) return fail(QEW_EINVAL, "bad strength");
+  if (N < 0) return fail(QEW_EINVAL, "N < 0");
+  if (N > 0 && (!d_did || !d_j || !d_cell || !d_frac || !d_out)) return fail(QEW_EINVAL, "NULL device pointer");
+  if (N > (int64_t(1) << 31) * 256) return fail(QEW_EINVAL, "N too large");
+  QEW_HIP(launch_force_eval(kind, strength, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32),
+                            precision, d_did, d_j, d_cell, d_frac, d_out, N,
+                            static_cast<hipStream_t>(stream)));
+  return QEW_OK;
+}
+
+void qew_plan_destroy(qew_plan_t* p) {
+  if (!p) return;
+  drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  delete p;
+}
+
+}  // extern "C"

@@ -334,3 +334,22 @@ def test_fp64_rounding_against_60_digit_evaluation(oracle, kind):
         u = new
     err = max(abs(float(u[j]) - r["u"][j]) for j in range(L))
     assert err < 1e-12
+
+
+def test_light_cone_window_matches_full_chain(oracle):
+    """A site after m steps depends only on sites within distance m (nearest-
+    neighbour coupling of the discretised Eq. (1)): the window evolution equals
+    the full periodic chain there, including across the wrap point."""
+    L, N = 300, 40
+    for kind in (0, 1):
+        full = oracle.run_sample(kind, 1.0, SEED, 3, L, 1.0, 0.05, 1.0, N, [])["u"]
+        for j in (0, 1, 57, 150, 298, 299):
+            assert oracle.site_after(kind, 1.0, SEED, 3, L, j, 1.0, 0.05, 1.0, N) == full[j]
+
+
+def test_mean_node_at_zero_is_initial_mean_force(oracle):
+    """v at step 0 from the flat start is f + strength * mean_j R(j, 0) for RF
+    (the spline at s = 0 returns the node)."""
+    L = 500
+    r = oracle.run_sample(0, 0.8, SEED, 2, L, 1.0, 0.05, 1.1, 0, [0])
+    assert abs(r["v"][0] - (1.1 + 0.8 * oracle.mean_node(0, SEED, 2, L, 0))) < 1e-14
