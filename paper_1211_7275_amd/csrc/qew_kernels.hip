@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(kBlock)
   const uint32_t id = t.did[s];
   const double f = t.f[s];
   const PlainPhys pp{ph.c, ph.dt, ph.strength};
-  const double K = floor(u[base + p0]);
+  const double K = u[base + p0];  // shift: the tile's first site (exactly 0 for a flat tile)
   double sf = 0.0, s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
@@ -382,7 +382,8 @@ __global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phy
   const uint32_t id = t.did[s];
   const float f = t.f32[s];
   const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
-  const int32_t K = b.cell[base + p0];
+  const int32_t Kc = b.cell[base + p0];  // shift: the tile's first site
+  const double Kr = (double)b.frac[base + p0];
   double sf = 0.0, s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
@@ -395,12 +396,12 @@ __global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phy
     const float F = split_force<KIND>(c, r, b.cell[base + jm], b.frac[base + jm], b.cell[base + jp],
                                       b.frac[base + jp], n0, n1, n2, n3, f, sp);
     sf += (double)F;
-    const double x = (double)(c - K) + (double)r;
+    const double x = (double)(c - Kc) + ((double)r - Kr);  // exact
     s1 += x;
     s2 += x * x;
   }
   block_sum3(sf, s1, s2, lds);
-  if (threadIdx.x == 0) part[tile] = Partial{sf, s1, s2, (double)K};
+  if (threadIdx.x == 0) part[tile] = Partial{sf, s1, s2, (double)Kc + Kr};
 }
 
 // Per-sample combine of tile partials: mean and sum of squared deviations by

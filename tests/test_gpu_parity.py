@@ -6,7 +6,9 @@ Tolerances (from the arithmetic of each path):
     within 1e-10 relative (same operation order; only libm-vs-device rounding of
     log/cos for random-bond nodes and the order of the FP64 reductions differ).
   - FP32 split path: per site within 1e-3 absolute at the 10^4-step horizon,
-    ensemble v(t) and w2(t) within 1e-3 relative.
+    ensemble v(t) and w2(t) within 1e-3 relative (v relative to max(|v|, 1e-3):
+    the FP32 force has ~1e-7 absolute rounding, so a pinned sample's v -> 0 is
+    compared with an absolute floor of 1e-6).
   - fused vs one-step split kernels, graph replay vs direct launches, resume
     vs uninterrupted: bit-identical (same site-update arithmetic).
 """
@@ -228,22 +230,51 @@ def test_random_bond_parity(qew, oracle):
     e32 = np.max(np.abs(b["u"][0] - ref["u"][0]))
     say("  fp32 per-site err", e32)
     assert e32 <= 1e-3
-    for key in ("v", "w2"):
-        assert rel_err(b[key], ref[key]) <= 1e-3
+    # v -> 0 as the sample pins; FP32 forces carry ~1e-7 absolute rounding, so
+    # v is compared relative to max(|v|, 1e-3) (absolute floor 1e-6).
+    assert rel_err(b["v"], ref["v"], floor=1e-3) <= 1e-3
+    assert rel_err(b["w2"], ref["w2"]) <= 1e-3
 
 
 # ----------------------------------------------------------- closed forms --
 
+def _split_rigid(dt, f, n):
+    """u after n split steps of a flat line with no disorder, in FP32 arithmetic:
+    the offset takes r + dt*f rounded once to FP32 (a fused multiply-add, exact
+    here in FP64 before the final rounding) and whole units move to the cell."""
+    cell, r = 0, np.float32(0.0)
+    dtf, ff = np.float32(dt), np.float32(f)
+    for _ in range(n):
+        rn = np.float32(np.float64(dtf) * np.float64(ff) + np.float64(r))
+        fl = np.floor(rn)
+        r = np.float32(rn - fl)
+        cell += int(fl)
+        if r >= 1.0:
+            r, cell = np.float32(r - 1.0), cell + 1
+    return cell + float(r)
+
+
 def test_zero_disorder_flat_line(qew):
-    p = workloads.custom(0, [1000, 4096], [1.0, 0.5], 500, [0, 1, 10, 499, 500], SEED, strength=0.0)
+    """strength 0, flat start: the line moves rigidly, v = f exactly, w2 = 0."""
+    N = 500
+    p = workloads.custom(0, [1000, 4096], [1.0, 0.5], N, [0, 1, 10, 499, 500], SEED, strength=0.0)
     for prec, path in [(qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP), (qew.QEW_FP32_SPLIT, qew.QEW_FUSED),
                        (qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP)]:
         say("flat line, strength 0", prec, path)
         out = run_gpu(qew, p, prec, path, k=16 if path else 0, tile=1024 if path else 0)
         assert np.all(out["v"] == np.array([[1.0], [0.5]]))
-        assert np.all(out["w2"] <= 1e-24)
+        assert np.all(out["w2"] == 0.0)
         for s, f in enumerate((1.0, 0.5)):
-            assert np.all(np.abs(out["u"][s] - 500 * 0.05 * f) <= 1e-9)
+            if prec == qew.QEW_FP64_PLAIN:
+                x = 0.0
+                for _ in range(N):
+                    x = x + 0.05 * f
+                assert np.all(out["u"][s] == x)
+            else:
+                # dt = 0.05 is not exact in FP32: within 5e-5 of N dt f, and
+                # exactly the FP32 evaluation of the same steps
+                assert np.all(np.abs(out["u"][s] - N * 0.05 * f) <= 5e-5)
+                assert np.all(out["u"][s] == _split_rigid(0.05, f, N))
 
 
 def test_zero_disorder_fourier_mode(qew):
@@ -254,7 +285,7 @@ def test_zero_disorder_fourier_mode(qew):
     meas = np.array([0, 1, 50, 399, 400])
     p = workloads.custom(0, [L], f, N, meas, SEED, strength=0.0)
     for prec, path, tol in [(qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 1e-12),
-                            (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 1e-5)]:
+                            (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 5e-5)]:
         say("fourier mode", prec, path)
         sim = qew.Simulation(p, precision=prec, path=path, k=16, tile=1024)
         try:
@@ -307,7 +338,7 @@ def test_full_size_l2e22_sampled_sites(qew, oracle):
     sampled sites against the oracle's light-cone windows, v(0) against the
     exact mean of the step-0 nodes, and d ubar = dt v at every step."""
     N = 48
-    p = workloads.config3(n_steps=N, n_meas=N + 1)
+    p = workloads.config3(n_steps=N, n_meas=2)
     p["meas_steps"] = np.arange(0, N + 1)
     L = int(p["L"][0])
     say("full size L=2^22 x 4, fused, autotuned, 48 steps")
