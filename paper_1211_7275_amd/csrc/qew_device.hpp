@@ -110,22 +110,41 @@ __device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, u
 // FP32 form: value = p1 + s (a1 + s (a2 + s a3)) with
 //   a1 = (p2 - p0) / 2, a2 = p0 - 5/2 p1 + 2 p2 - 1/2 p3,
 //   a3 = 3/2 (p1 - p2) + 1/2 (p3 - p0);  slope = a1 + s (2 a2 + 3 a3 s).
-// RF uses the value, RB the slope (F_p = -dU/du).
+// RF uses the value, RB the slope (F_p = -dU/du).  The coefficients of a
+// cell are computed once (spline_coef) and evaluated every step
+// (spline_eval); every kernel goes through these two functions, so a cached
+// coefficient set gives exactly the force a fresh evaluation gives.
+//   RF: {x, y, z, w} = {p1, a1, a2, a3}
+//   RB: {x, y, z, w} = {0, a1, 2 a2, 3 a3}
 // ---------------------------------------------------------------------------
 template <int KIND>
-__device__ __forceinline__ float spline_f32(float p0, float p1, float p2, float p3, float s) {
+__device__ __forceinline__ float4 spline_coef(float p0, float p1, float p2, float p3) {
   const float a1 = 0.5f * (p2 - p0);
   const float d30 = p3 - p0;
   const float d12 = p1 - p2;
   if constexpr (KIND == kRF) {
     const float a2 = fmaf(-0.5f, p3, fmaf(2.0f, p2, fmaf(-2.5f, p1, p0)));
     const float a3 = fmaf(1.5f, d12, 0.5f * d30);
-    return fmaf(s, fmaf(s, fmaf(s, a3, a2), a1), p1);
+    return make_float4(p1, a1, a2, a3);
   } else {
     const float b2 = fmaf(-1.0f, p3, fmaf(4.0f, p2, fmaf(-5.0f, p1, 2.0f * p0)));
     const float b3 = fmaf(4.5f, d12, 1.5f * d30);
-    return fmaf(s, fmaf(s, b3, b2), a1);
+    return make_float4(0.0f, a1, b2, b3);
   }
+}
+
+template <int KIND>
+__device__ __forceinline__ float spline_eval(const float4& a, float s) {
+  if constexpr (KIND == kRF) {
+    return fmaf(s, fmaf(s, fmaf(s, a.w, a.z), a.y), a.x);
+  } else {
+    return fmaf(s, fmaf(s, a.w, a.z), a.y);
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ float spline_f32(float p0, float p1, float p2, float p3, float s) {
+  return spline_eval<KIND>(spline_coef<KIND>(p0, p1, p2, p3), s);
 }
 
 // FP64 form, same operation order as the textbook polynomial
@@ -153,14 +172,14 @@ struct SplitPhys {
 };
 
 // Total force of Eq. (1) on a split site (cell c, offset r) with neighbours
-// (cl, rl), (cr, rr) and nodes p0..p3 of its cell.  The integer part of the
-// Laplacian is exact; the offsets carry the fraction.
+// (cl, rl), (cr, rr) and spline coefficients `a` of its cell.  The integer
+// part of the Laplacian is exact; the offsets carry the fraction.
 template <int KIND>
 __device__ __forceinline__ float split_force(int32_t c, float r, int32_t cl, float rl, int32_t cr,
-                                             float rr, float p0, float p1, float p2, float p3,
-                                             float f, const SplitPhys& ph) {
+                                             float rr, const float4& a, float f,
+                                             const SplitPhys& ph) {
   const float lap = (float)((cl - c) + (cr - c)) + ((rl + rr) - 2.0f * r);
-  const float sp = spline_f32<KIND>(p0, p1, p2, p3, r);
+  const float sp = spline_eval<KIND>(a, r);
   return fmaf(ph.c, lap, fmaf(ph.sgn_str, sp, f));
 }
 

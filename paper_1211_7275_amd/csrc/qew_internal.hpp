@@ -58,6 +58,7 @@ hipError_t launch_step_split1(const Tables& t, SplitBuf in, SplitBuf out, const 
 hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
                              int tile, int halo, int nsub, int grid, hipStream_t st);
 int fused_max_grid(int tile);
+bool fused_fits(int tile);  // static LDS of the tile's kernel within the device limit
 hipError_t launch_meas_plain(const Tables& t, const double* u, const Phys& ph, int kind,
                              Partial* part, hipStream_t st);
 hipError_t launch_meas_split(const Tables& t, SplitBuf b, const Phys& ph, int kind, Partial* part,

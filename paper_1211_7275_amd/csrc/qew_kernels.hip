@@ -41,13 +41,6 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Orders this wave's LDS accesses (all lanes) before and after the point.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Block-wide deterministic FP64 sum of three values (fixed reduction order).
 __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* lds /*[3*4]*/) {
   a = wave_sum_f64(a);
@@ -71,13 +64,6 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
     b = y;
     c = z;
   }
-}
-
-// Position in the sample of a lane's i-th site (pos0 < L).
-__device__ __forceinline__ int site_of(int pos0, int i, int L, bool tiny) {
-  int j = pos0 + i;
-  if (tiny) return j % L;
-  return j >= L ? j - L : j;
 }
 
 }  // namespace
@@ -177,8 +163,9 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
     float r = in.frac[base + j];
     float n0, n1, n2, n3;
     nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+    const float4 a = spline_coef<KIND>(n0, n1, n2, n3);
     const float F = split_force<KIND>(c, r, in.cell[base + jm], in.frac[base + jm],
-                                      in.cell[base + jp], in.frac[base + jp], n0, n1, n2, n3, f, sp);
+                                      in.cell[base + jp], in.frac[base + jp], a, f, sp);
     split_advance(c, r, F, sp.dt);
     out.cell[base + j] = c;
     out.frac[base + j] = r;
@@ -187,18 +174,45 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 
 // ---------------------------------------------------------------------------
 // Fused temporally blocked kernel (split precision).
+//
+// One workgroup owns one tile of T = 256 P consecutive sites of one sample at
+// a time: positions p0 - halo .. p0 - halo + T - 1 (periodic in the sample).
+// Thread t holds sites t P .. t P + P - 1 in registers: cell, offset and the
+// spline coefficients of the current cell.  The four raw nodes of every site
+// live in LDS, slot-major (node index i * 256 + t).  Each sub-step:
+//   1. every site takes one Euler step (neighbours within a thread directly,
+//      across lanes by wave shuffles, across waves through LDS);
+//   2. a site whose cell changed posts a request (its LDS node index, new
+//      cell, kind of move) into its wave's region of the request list;
+//   3. barrier; the whole workgroup serves all requests: shift the node
+//      window, generate the missing node (all four after a jump of two or
+//      more cells), store the window, and write the new coefficients into the
+//      request slot;
+//   4. barrier; each requester reads its new coefficients.
+// A sub-step with no request at all skips 3-4.  After nsub <= halo
+// sub-steps the sites within `halo` of either tile end hold garbage (the tile
+// ends reflect), and the valid part [halo, halo + len) is written back with
+// its nodes.
 // ---------------------------------------------------------------------------
-template <int KIND, int P>
-__global__ void __launch_bounds__(kBlock)
-    k_step_fused(Tables t, SplitBuf in, SplitBuf out, Phys ph, int halo, int nsub) {
-  __shared__ int2 s_task[kBlock / 64][64 * P];
-  const int lane = threadIdx.x & 63;
-  const int wv = uniform_i32(threadIdx.x >> 6);
-  int2* task = s_task[wv];
-  const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
-  const int waves_in_grid = gridDim.x * (kBlock / 64);
+constexpr int kReqPerWave = 256;
 
-  for (int ti = blockIdx.x * (kBlock / 64) + wv; ti < t.n_ft; ti += waves_in_grid) {
+template <int KIND, int P>
+__global__ void __launch_bounds__(kBlock, 2)
+    k_step_fused(Tables t, SplitBuf in, SplitBuf out, Phys ph, int halo, int nsub) {
+  constexpr int T = kBlock * P;
+  constexpr int NW = kBlock / 64;
+  constexpr int RQ = kReqPerWave;
+  __shared__ float4 s_nodes[T];
+  __shared__ int4 s_req[NW * RQ];
+  __shared__ int s_count[2][NW];
+  __shared__ int2 s_edge[2][NW][2];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = uniform_i32(tid >> 6);
+  const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
+
+  for (int ti = blockIdx.x; ti < t.n_ft; ti += gridDim.x) {
     const int s = uniform_i32(t.ft_s[ti]);
     const int p0 = uniform_i32(t.ft_p0[ti]);
     const int len = uniform_i32(t.ft_len[ti]);
@@ -206,137 +220,212 @@ __global__ void __launch_bounds__(kBlock)
     const int64_t base = uniform_i64(t.off[s]);
     const uint32_t id = (uint32_t)uniform_i32((int)t.did[s]);
     const float f = t.f32[s];
-
-    // First site of this lane, as a position in the sample (periodic).
-    int pos0 = (p0 - halo + lane * P) % L;
-    if (pos0 < 0) pos0 += L;
-    const bool tiny = L < P;  // wave-uniform: a lane's sites wrap more than once
+    const int start = p0 - halo;
+    int start_mod = start % L;
+    if (start_mod < 0) start_mod += L;
+    const bool contiguous = start >= 0 && start + T <= L && (start & 3) == 0;
 
     int32_t c[P];
-    float r[P], n0[P], n1[P], n2[P], n3[P];
-    {
-      int pos = pos0;
+    float r[P];
+    float4 a[P];
+    if (contiguous) {
+      const int64_t g = base + start + tid * P;
+#pragma unroll
+      for (int v = 0; v < P / 4; ++v) {
+        const int4 cv = *reinterpret_cast<const int4*>(in.cell + g + 4 * v);
+        const float4 rv = *reinterpret_cast<const float4*>(in.frac + g + 4 * v);
+        c[4 * v] = cv.x; c[4 * v + 1] = cv.y; c[4 * v + 2] = cv.z; c[4 * v + 3] = cv.w;
+        r[4 * v] = rv.x; r[4 * v + 1] = rv.y; r[4 * v + 2] = rv.z; r[4 * v + 3] = rv.w;
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const float4 nd = in.nodes[g + i];
+        s_nodes[i * kBlock + tid] = nd;
+        a[i] = spline_coef<KIND>(nd.x, nd.y, nd.z, nd.w);
+      }
+    } else {
+      int pos = (start_mod + tid * P) % L;
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         c[i] = in.cell[base + pos];
         r[i] = in.frac[base + pos];
         const float4 nd = in.nodes[base + pos];
-        n0[i] = nd.x;
-        n1[i] = nd.y;
-        n2[i] = nd.z;
-        n3[i] = nd.w;
+        s_nodes[i * kBlock + tid] = nd;
+        a[i] = spline_coef<KIND>(nd.x, nd.y, nd.z, nd.w);
         pos = (pos + 1 == L) ? 0 : pos + 1;
       }
     }
+    if (lane == 0) s_edge[0][wv][0] = make_int2(c[0], __float_as_int(r[0]));
+    if (lane == 63) s_edge[0][wv][1] = make_int2(c[P - 1], __float_as_int(r[P - 1]));
+    __syncthreads();
 
     for (int sub = 0; sub < nsub; ++sub) {
-      // Neighbour values across lanes; the tile ends reflect (their garbage
-      // stays inside the halo, which moves inwards one site per sub-step).
+      const int par = sub & 1;
+      // Neighbours of this thread's end sites.  The tile ends reflect.
       int32_t cle = __shfl_up(c[P - 1], 1, 64);
       float rle = __shfl_up(r[P - 1], 1, 64);
       int32_t cre = __shfl_down(c[0], 1, 64);
       float rre = __shfl_down(r[0], 1, 64);
       if (lane == 0) {
-        cle = c[0];
-        rle = r[0];
+        if (wv > 0) {
+          const int2 e = s_edge[par][wv - 1][1];
+          cle = e.x;
+          rle = __int_as_float(e.y);
+        } else {
+          cle = c[0];
+          rle = r[0];
+        }
       }
       if (lane == 63) {
-        cre = c[P - 1];
-        rre = r[P - 1];
+        if (wv < NW - 1) {
+          const int2 e = s_edge[par][wv + 1][0];
+          cre = e.x;
+          rre = __int_as_float(e.y);
+        } else {
+          cre = c[P - 1];
+          rre = r[P - 1];
+        }
       }
 
+      // Euler step of every site; a site that changed cell posts a request.
+      uint64_t moved[P];
+      uint32_t nreq = 0u;  // wave-uniform
       int32_t pc = cle;
       float pr = rle;
-      uint32_t up = 0u, dn = 0u, big = 0u;
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const int32_t nc = (i + 1 < P) ? c[i + 1] : cre;
         const float nr = (i + 1 < P) ? r[i + 1] : rre;
-        const float F = split_force<KIND>(c[i], r[i], pc, pr, nc, nr, n0[i], n1[i], n2[i], n3[i],
-                                          f, sp);
+        const float F = split_force<KIND>(c[i], r[i], pc, pr, nc, nr, a[i], f, sp);
         const int32_t oc = c[i];
         pc = oc;
         pr = r[i];
         split_advance(c[i], r[i], F, sp.dt);
         const int32_t d = c[i] - oc;
-        up |= (uint32_t)(d == 1) << i;
-        dn |= (uint32_t)(d == -1) << i;
-        big |= (uint32_t)((d > 1) | (d < -1)) << i;
-      }
-
-      // Rare: a jump of two or more cells regenerates all four nodes.
-      if (__ballot(big != 0u)) {
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-          if ((big >> i) & 1u) {
-            const int j = site_of(pos0, i, L, tiny);
-            nodes_of<KIND>((uint32_t)j, c[i], id, ph, n0[i], n1[i], n2[i], n3[i]);
+        moved[i] = __ballot(d != 0);
+        if (d != 0) {
+          const uint32_t k = nreq + mbcnt64(moved[i]);
+          if (k < (uint32_t)RQ) {
+            const int code = (d == 1) ? 0 : ((d == -1) ? 1 : 2);
+            s_req[wv * RQ + k] = make_int4(i * kBlock + tid, c[i], code, 0);
           }
         }
+        nreq += (uint32_t)__popcll(moved[i]);
       }
+      if (lane == 0) {
+        s_edge[par ^ 1][wv][0] = make_int2(c[0], __float_as_int(r[0]));
+        s_count[par][wv] = (int)nreq;
+      }
+      if (lane == 63) s_edge[par ^ 1][wv][1] = make_int2(c[P - 1], __float_as_int(r[P - 1]));
+      __syncthreads();
 
-      // One new node per site that moved by one cell: gather the requests of
-      // the whole wave into LDS (lane-major, offsets from a wave prefix sum),
-      // generate them with all 64 lanes, and scatter them back.
-      const uint32_t chg = up | dn;
-      const uint32_t cnt = (uint32_t)__popc(chg);
-      uint32_t incl = cnt;
+      int cnt[NW];
+      int maxcnt = 0;
 #pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
+      for (int w = 0; w < NW; ++w) {
+        cnt[w] = s_count[par][w];
+        maxcnt = cnt[w] > maxcnt ? cnt[w] : maxcnt;
       }
-      const uint32_t ntask = __builtin_amdgcn_readlane(incl, 63);
-      const uint32_t lane_base = incl - cnt;
-      if (ntask != 0u) {
+      const int rounds = (maxcnt + RQ - 1) / RQ;
+      for (int rd = 0; rd < rounds; ++rd) {
+        const uint32_t lo = (uint32_t)(rd * RQ);
+        if (rd > 0) {  // overflow: post the requests of this round
+          uint32_t n = 0u;
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-          if ((chg >> i) & 1u) {
-            const int j = site_of(pos0, i, L, tiny);
-            const int32_t need = ((up >> i) & 1u) ? c[i] + 2 : c[i] - 1;
-            task[lane_base + __popc(chg & ((1u << i) - 1u))] = make_int2(j, need);
+          for (int i = 0; i < P; ++i) {
+            if ((moved[i] >> lane) & 1u) {
+              const uint32_t k = n + mbcnt64(moved[i]);
+              if (k >= lo && k < lo + RQ) {  // served by full regeneration of the window
+                s_req[wv * RQ + (k - lo)] = make_int4(i * kBlock + tid, c[i], 2, 0);
+              }
+            }
+            n += (uint32_t)__popcll(moved[i]);
           }
+          __syncthreads();
         }
-        wave_lds_sync();
-        for (uint32_t q = lane; q < ntask; q += 64) {
-          const int2 tk = task[q];
-          float v = 0.0f;
-          if (ph.strength != 0.0) v = node_f32<KIND>((uint32_t)tk.x, tk.y, id, ph.k0, ph.k1);
-          task[q].x = __float_as_int(v);
+        // Serve the requests of this round with the whole workgroup.
+        int pre[NW + 1];
+        pre[0] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          int cw = cnt[w] - rd * RQ;
+          cw = cw < 0 ? 0 : (cw > RQ ? RQ : cw);
+          pre[w + 1] = pre[w] + cw;
         }
-        wave_lds_sync();
+        for (int q = tid; q < pre[NW]; q += kBlock) {
+          int w = 0;
+#pragma unroll
+          for (int x = 1; x < NW; ++x) w += (q >= pre[x]) ? 1 : 0;
+          const int slot = w * RQ + (q - pre[w]);
+          const int4 rq = s_req[slot];
+          const int ni = rq.x;
+          const int32_t cell = rq.y;
+          const int lp = (ni % kBlock) * P + ni / kBlock;  // tile-local position
+          int j = start_mod + lp;
+          if (j >= L) j -= L;
+          if (j >= L) j %= L;
+          float4 w4 = s_nodes[ni];
+          if (rq.z == 0) {
+            w4 = make_float4(w4.y, w4.z, w4.w, node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
+          } else if (rq.z == 1) {
+            w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1), w4.x, w4.y, w4.z);
+          } else {
+            w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1),
+                             node_f32<KIND>((uint32_t)j, cell, id, ph.k0, ph.k1),
+                             node_f32<KIND>((uint32_t)j, cell + 1, id, ph.k0, ph.k1),
+                             node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
+          }
+          s_nodes[ni] = w4;
+          const float4 co = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w);
+          s_req[slot] = make_int4(__float_as_int(co.x), __float_as_int(co.y), __float_as_int(co.z),
+                                  __float_as_int(co.w));
+        }
+        __syncthreads();
+        // Requesters read their new coefficients.
+        uint32_t n = 0u;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-          if ((chg >> i) & 1u) {
-            const float v = __int_as_float(task[lane_base + __popc(chg & ((1u << i) - 1u))].x);
-            if ((up >> i) & 1u) {
-              n0[i] = n1[i];
-              n1[i] = n2[i];
-              n2[i] = n3[i];
-              n3[i] = v;
-            } else {
-              n3[i] = n2[i];
-              n2[i] = n1[i];
-              n1[i] = n0[i];
-              n0[i] = v;
+          if ((moved[i] >> lane) & 1u) {
+            const uint32_t k = n + mbcnt64(moved[i]);
+            if (k >= lo && k < lo + RQ) {
+              const int4 v = s_req[wv * RQ + (k - lo)];
+              a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
+                                 __int_as_float(v.w));
             }
           }
+          n += (uint32_t)__popcll(moved[i]);
         }
-        wave_lds_sync();
+        if (rd + 1 < rounds) __syncthreads();
       }
     }
 
     // Write the valid part: tile-local q in [halo, halo + len).
+    int qb = tid * P;
+    asm volatile("" : "+v"(qb));
+    const int64_t g0 = base + p0 + (qb - halo);
+    if (qb >= halo && qb + P <= halo + len && (g0 & 3) == 0) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int q = lane * P + i;
-      if (q >= halo && q < halo + len) {
-        const int64_t g = base + p0 + (q - halo);
-        out.cell[g] = c[i];
-        out.frac[g] = r[i];
-        out.nodes[g] = make_float4(n0[i], n1[i], n2[i], n3[i]);
+      for (int v = 0; v < P / 4; ++v) {
+        *reinterpret_cast<int4*>(out.cell + g0 + 4 * v) =
+            make_int4(c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]);
+        *reinterpret_cast<float4*>(out.frac + g0 + 4 * v) =
+            make_float4(r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) out.nodes[g0 + i] = s_nodes[i * kBlock + tid];
+    } else {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int q = qb + i;
+        if (q >= halo && q < halo + len) {
+          const int64_t g = base + p0 + (q - halo);
+          out.cell[g] = c[i];
+          out.frac[g] = r[i];
+          out.nodes[g] = s_nodes[i * kBlock + tid];
+        }
       }
     }
+    __syncthreads();  // s_nodes and s_edge are reused by the next tile
   }
 }
 
@@ -393,8 +482,9 @@ __global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phy
     const float r = b.frac[base + j];
     float n0, n1, n2, n3;
     nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+    const float4 a = spline_coef<KIND>(n0, n1, n2, n3);
     const float F = split_force<KIND>(c, r, b.cell[base + jm], b.frac[base + jm], b.cell[base + jp],
-                                      b.frac[base + jp], n0, n1, n2, n3, f, sp);
+                                      b.frac[base + jp], a, f, sp);
     sf += (double)F;
     const double x = (double)(c - Kc) + ((double)r - Kr);  // exact
     s1 += x;
@@ -547,23 +637,34 @@ int fused_max_grid(int tile) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* fn = tile == 512 ? fused_ptr<kRF, 8>() : tile == 1024 ? fused_ptr<kRF, 16>() : fused_ptr<kRF, 32>();
+  const void* fn = tile == 1024 ? fused_ptr<kRF, 4>() : tile == 2048 ? fused_ptr<kRF, 8>() : fused_ptr<kRF, 16>();
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess) return 0;
   if (per_cu < 1) per_cu = 1;
   return cus * per_cu;
+}
+
+bool fused_fits(int tile) {
+  int dev = 0, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return false;
+  hipFuncAttributes attr{};
+  const void* fn = tile == 1024 ? fused_ptr<kRF, 4>() : tile == 2048 ? fused_ptr<kRF, 8>() : fused_ptr<kRF, 16>();
+  if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return false;
+  return (int)attr.sharedSizeBytes <= max_lds;
 }
 
 hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
                              int tile, int halo, int nsub, int grid, hipStream_t st) {
   const dim3 g(grid), b(kBlock);
   if (kind == kRF) {
-    if (tile == 512) hipLaunchKernelGGL((k_step_fused<kRF, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRF, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else hipLaunchKernelGGL((k_step_fused<kRF, 32>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRF, 4>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<kRF, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else hipLaunchKernelGGL((k_step_fused<kRF, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
   } else {
-    if (tile == 512) hipLaunchKernelGGL((k_step_fused<kRB, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRB, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else hipLaunchKernelGGL((k_step_fused<kRB, 32>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRB, 4>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<kRB, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
+    else hipLaunchKernelGGL((k_step_fused<kRB, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
   }
   return hipGetLastError();
 }

@@ -46,7 +46,7 @@ qew_status fail(qew_status st, const char* fmt, ...) {
 
 constexpr int64_t kMaxL = int64_t(1) << 30;
 constexpr int kGraphLaunches = 16;
-constexpr int kTuneTiles[3] = {512, 1024, 2048};
+constexpr int kTuneTiles[3] = {1024, 2048, 4096};
 constexpr int kTuneK[3] = {8, 16, 32};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -280,9 +280,10 @@ hipError_t step_launch(const qew_plan_t* p, void* ws, int from, int nsub, hipStr
 
 qew_status ensure_fused_grid(qew_plan_t* p) {
   if (!fused(p)) return QEW_OK;
+  if (!fused_fits(p->tile)) return fail(QEW_EUNSUPPORTED, "tile %d needs more LDS than this device allows", p->tile);
   const int maxg = fused_max_grid(p->tile);
   if (maxg <= 0) return fail(QEW_EDEVICE, "could not query occupancy of the fused kernel");
-  const int need = (int)((p->ft_s.size() + (kBlock / 64) - 1) / (kBlock / 64));
+  const int need = (int)p->ft_s.size();
   p->fused_grid = std::max(1, std::min(need, maxg));
   return QEW_OK;
 }
@@ -415,8 +416,8 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
   if (pr->path == QEW_FUSED && pr->precision != QEW_FP32_SPLIT)
     return fail(QEW_EUNSUPPORTED, "the fused path runs in FP32 split precision only");
   if (pr->k < 0 || pr->k > kMaxHalo) return fail(QEW_EINVAL, "k must be in [0, %d]", kMaxHalo);
-  if (pr->tile != 0 && pr->tile != 512 && pr->tile != 1024 && pr->tile != 2048)
-    return fail(QEW_EINVAL, "tile must be 0, 512, 1024 or 2048");
+  if (pr->tile != 0 && pr->tile != 1024 && pr->tile != 2048 && pr->tile != 4096)
+    return fail(QEW_EINVAL, "tile must be 0, 1024, 2048 or 4096");
   if (pr->k > 0 && pr->tile > 0 && 4 * pr->k > pr->tile) return fail(QEW_EINVAL, "need 4*k <= tile");
   if (pr->flags & ~(QEW_FLAG_NO_GRAPH | QEW_FLAG_TIMING)) return fail(QEW_EINVAL, "unknown flag bits");
   for (int32_t s = 0; s < pr->n_samples; ++s) {
@@ -483,7 +484,7 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
       return fail(QEW_EINVAL, "too many fused tiles");
     }
     p->ft_capacity = (int32_t)cap;
-    const int tile0 = p->tile_req ? p->tile_req : 1024;
+    const int tile0 = p->tile_req ? p->tile_req : 2048;
     int k0 = p->k_req ? p->k_req : 16;
     if (4 * k0 > tile0) k0 = tile0 / 4;
     build_fused_tiles(p, tile0, k0);
@@ -530,6 +531,7 @@ qew_status qew_autotune(qew_plan_t* p, void* ws, size_t bytes, void* stream) {
   int best_tile = p->tile, best_k = p->k;
   for (int tile : kTuneTiles) {
     if (p->tile_req && tile != p->tile_req) continue;
+    if (!fused_fits(tile)) continue;
     for (int kc : kTuneK) {
       const int k = p->k_req ? p->k_req : kc;
       if (4 * k > tile) continue;
@@ -563,6 +565,7 @@ qew_status qew_autotune(qew_plan_t* p, void* ws, size_t bytes, void* stream) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != QEW_OK) return rc;
+  if (best < 0.0) return fail(QEW_EUNSUPPORTED, "no fused tile width fits this device's LDS");
   build_fused_tiles(p, best_tile, best_k);
   p->autotuned = 1;
   p->state_ws = nullptr;  // the state was overwritten

@@ -84,8 +84,9 @@ def test_plan_rejects_bad_path_options():
     assert _plan_status(p, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_FUSED)[0] == qew.QEW_EUNSUPPORTED
     assert _plan_status(p, k=65)[0] == qew.QEW_EINVAL
     assert _plan_status(p, tile=700)[0] == qew.QEW_EINVAL
-    assert _plan_status(p, k=200, tile=512)[0] == qew.QEW_EINVAL
-    assert _plan_status(p, k=130, tile=512)[0] == qew.QEW_EINVAL
+    assert _plan_status(p, k=64, tile=1024)[0] == 0
+    assert _plan_status(p, tile=512)[0] == qew.QEW_EINVAL
+    assert _plan_status(p, k=130, tile=4096)[0] == qew.QEW_EINVAL
     assert _plan_status(p, flags=64)[0] == qew.QEW_EINVAL
     assert _plan_status(p, precision=5)[0] == qew.QEW_EINVAL
 
@@ -104,7 +105,7 @@ def test_plan_null_arguments():
 
 def test_plan_info_and_workspace_size():
     p = workloads.custom(0, [1024, 3000, 70000], 1.0, 10, [10], 1)
-    pr, keep = qew.make_problem(p, k=16, tile=1024)
+    pr, keep = qew.make_problem(p, k=16, tile=1024)  # 1024-site workgroup tiles
     plan = qew.qew_plan(pr)
     try:
         info = qew.qew_plan_info_get(plan)

@@ -154,7 +154,7 @@ def test_config0_fp32_split_parity(qew, c0_oracle, path):
 
 # -------------------------------------------- fused == one-step (bitwise) --
 
-GEOMS = [(1, 512), (5, 512), (8, 512), (16, 1024), (32, 1024), (32, 2048), (64, 2048)]
+GEOMS = [(1, 1024), (5, 1024), (8, 1024), (16, 2048), (32, 2048), (32, 4096), (64, 4096)]
 SIZES = [3, 5, 31, 64, 100, 511, 1000, 1024, 1500, 5000]
 
 
@@ -175,7 +175,7 @@ def test_fused_bit_identical_to_one_step(qew, kind):
 
 def test_graph_replay_matches_direct_launches(qew):
     p = workloads.custom(0, [4096, 3000, 70000], 1.0, 2500, workloads.log_steps(2500, 20), SEED + 6)
-    for prec, path, k, tile in [(qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 8, 512),
+    for prec, path, k, tile in [(qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 8, 1024),
                                 (qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP, 0, 0),
                                 (qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 0, 0)]:
         say("graph vs direct", prec, path, k, tile)
@@ -389,12 +389,12 @@ def test_edge_cases(qew):
     p = workloads.custom(0, [64, 3], 1.0, 0, [0], SEED)
     for prec, path in [(qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP), (qew.QEW_FP32_SPLIT, qew.QEW_FUSED)]:
         say("edge: zero steps", prec, path)
-        out = run_gpu(qew, p, prec, path, k=8, tile=512)
+        out = run_gpu(qew, p, prec, path, k=8, tile=1024)
         assert np.all(out["w2"] == 0.0)
         assert np.all(np.concatenate(out["u"]) == 0.0)
     # no measurements at all
     p = workloads.custom(1, [100], 1.0, 50, [], SEED)
     say("edge: no measurements")
-    out = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=8, tile=512)
+    out = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=8, tile=1024)
     assert out["v"].shape == (1, 0)
     assert np.all(np.isfinite(out["u"][0]))
