@@ -145,7 +145,7 @@ def parity_check(qew):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100_000)
+    ap.add_argument("--steps", type=int, default=1_000_000)
     ap.add_argument("--warmup", type=int, default=512)
     ap.add_argument("--plain-steps", type=int, default=2000)
     ap.add_argument("--skip-plain", action="store_true")

@@ -22,15 +22,15 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose=False, extra=()):
-    os.makedirs(LIBDIR, exist_ok=True)
+def build(verbose=False, extra=(), out=LIB):
+    os.makedirs(os.path.dirname(out), exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, *HIPCC_FLAGS, *extra, *SOURCES, "-o", LIB + ".tmp"]
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, *SOURCES, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

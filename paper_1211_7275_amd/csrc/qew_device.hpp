@@ -178,7 +178,8 @@ template <int KIND>
 __device__ __forceinline__ float split_force(int32_t c, float r, int32_t cl, float rl, int32_t cr,
                                              float rr, const float4& a, float f,
                                              const SplitPhys& ph) {
-  const float lap = (float)((cl - c) + (cr - c)) + ((rl + rr) - 2.0f * r);
+  // (rl + rr) - 2 r rounded once (2 r is exact), written as one FMA.
+  const float lap = (float)((cl - c) + (cr - c)) + fmaf(-2.0f, r, rl + rr);
   const float sp = spline_eval<KIND>(a, r);
   return fmaf(ph.c, lap, fmaf(ph.sgn_str, sp, f));
 }

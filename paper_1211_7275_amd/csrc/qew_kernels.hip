@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 //   1. every site takes one Euler step (neighbours within a thread directly,
 //      across lanes by wave shuffles, across waves through LDS);
 //   2. a site whose cell changed posts a request (its LDS node index, new
-//      cell, kind of move) into its wave's region of the request list;
+//      cell, old cell) into its wave's region of the request list;
 //   3. barrier; the whole workgroup serves all requests: shift the node
 //      window, generate the missing node (all four after a jump of two or
 //      more cells), store the window, and write the new coefficients into the
@@ -194,10 +194,18 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 // ends reflect), and the valid part [halo, halo + len) is written back with
 // its nodes.
 // ---------------------------------------------------------------------------
-constexpr int kReqPerWave = 256;
+// Request slots per wave and sub-step (more requests are served in extra
+// rounds), and the occupancy target (waves per SIMD) of the fused kernel.
+#ifndef QEW_REQ_PER_WAVE
+#define QEW_REQ_PER_WAVE 64
+#endif
+#ifndef QEW_FUSED_MIN_WAVES
+#define QEW_FUSED_MIN_WAVES 4
+#endif
+constexpr int kReqPerWave = QEW_REQ_PER_WAVE;
 
 template <int KIND, int P>
-__global__ void __launch_bounds__(kBlock, 2)
+__global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
     k_step_fused(Tables t, SplitBuf in, SplitBuf out, Phys ph, int halo, int nsub) {
   constexpr int T = kBlock * P;
   constexpr int NW = kBlock / 64;
@@ -301,14 +309,10 @@ __global__ void __launch_bounds__(kBlock, 2)
         pc = oc;
         pr = r[i];
         split_advance(c[i], r[i], F, sp.dt);
-        const int32_t d = c[i] - oc;
-        moved[i] = __ballot(d != 0);
-        if (d != 0) {
+        moved[i] = __ballot(c[i] != oc);
+        if (c[i] != oc) {
           const uint32_t k = nreq + mbcnt64(moved[i]);
-          if (k < (uint32_t)RQ) {
-            const int code = (d == 1) ? 0 : ((d == -1) ? 1 : 2);
-            s_req[wv * RQ + k] = make_int4(i * kBlock + tid, c[i], code, 0);
-          }
+          if (k < (uint32_t)RQ) s_req[wv * RQ + k] = make_int4(i * kBlock + tid, c[i], oc, 0);
         }
         nreq += (uint32_t)__popcll(moved[i]);
       }
@@ -323,7 +327,7 @@ __global__ void __launch_bounds__(kBlock, 2)
       int maxcnt = 0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        cnt[w] = s_count[par][w];
+        cnt[w] = uniform_i32(s_count[par][w]);
         maxcnt = cnt[w] > maxcnt ? cnt[w] : maxcnt;
       }
       const int rounds = (maxcnt + RQ - 1) / RQ;
@@ -336,7 +340,7 @@ __global__ void __launch_bounds__(kBlock, 2)
             if ((moved[i] >> lane) & 1u) {
               const uint32_t k = n + mbcnt64(moved[i]);
               if (k >= lo && k < lo + RQ) {  // served by full regeneration of the window
-                s_req[wv * RQ + (k - lo)] = make_int4(i * kBlock + tid, c[i], 2, 0);
+                s_req[wv * RQ + (k - lo)] = make_int4(i * kBlock + tid, c[i], c[i], 0);
               }
             }
             n += (uint32_t)__popcll(moved[i]);
@@ -357,17 +361,18 @@ __global__ void __launch_bounds__(kBlock, 2)
 #pragma unroll
           for (int x = 1; x < NW; ++x) w += (q >= pre[x]) ? 1 : 0;
           const int slot = w * RQ + (q - pre[w]);
-          const int4 rq = s_req[slot];
+          const int4 rq = s_req[slot];  // {node index, new cell, old cell}
           const int ni = rq.x;
           const int32_t cell = rq.y;
+          const int32_t move = rq.y - rq.z;  // +1, -1, or anything else: regenerate all four
           const int lp = (ni % kBlock) * P + ni / kBlock;  // tile-local position
           int j = start_mod + lp;
           if (j >= L) j -= L;
           if (j >= L) j %= L;
           float4 w4 = s_nodes[ni];
-          if (rq.z == 0) {
+          if (move == 1) {
             w4 = make_float4(w4.y, w4.z, w4.w, node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
-          } else if (rq.z == 1) {
+          } else if (move == -1) {
             w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1), w4.x, w4.y, w4.z);
           } else {
             w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1),

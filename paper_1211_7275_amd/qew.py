@@ -12,7 +12,8 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libqew.so")
+# QEW_LIB_PATH selects another build of the same library (A/B timing of builds).
+LIB_PATH = os.environ.get("QEW_LIB_PATH") or os.path.join(_HERE, "lib", "libqew.so")
 
 QEW_OK = 0
 QEW_EINVAL = -1
