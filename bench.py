@@ -45,6 +45,32 @@ OPS_NODE_RB = 68
 HORIZON = 1_000_000
 N_POINTS = 200
 
+KERNEL_SOURCES = ("paper_1211_7275_amd/csrc/qew_kernels.hip", "paper_1211_7275_amd/csrc/qew_device.hpp")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_fused_L2e22x4.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(k, tile):
+    """HBM bytes per fused launch measured by rocprofv3 (FETCH_SIZE/WRITE_SIZE,
+    copy-calibrated) for this kernel source and geometry, else None."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    want = f"k={k} tile={tile} source={kernel_source_hash()}"
+    for ln in open(TRAFFIC_SUMMARY):
+        if ln.startswith("traffic_per_launch ") and want in ln:
+            for tok in ln.split():
+                if tok.startswith("bytes="):
+                    return int(tok[6:])
+    return None
+
 
 def bench_problem(steps, L=1 << 22, samples=4):
     p = workloads.config3(n_steps=HORIZON, n_meas=N_POINTS, samples=samples, L=L)
@@ -90,9 +116,10 @@ def fused_roofline(kind, st, info, out, steps):
     achieved = per_update * updates_per_launch / (launch_ms * 1e-3) / 1e12
     peak = VALU_LANE_OPS / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "unit": "TOP/s", "frac": round(achieved / peak, 4),
+            "traffic": committed_traffic(info.k, info.tile),
             "ops_per_update": round(per_update, 3), "launch_ms": round(launch_ms, 5),
-            "k": info.k, "tile": info.tile}
+            "launches": int(st.step_launches), "k": info.k, "tile": info.tile}
 
 
 def plain_roofline(st, info, steps):
@@ -102,7 +129,7 @@ def plain_roofline(st, info, steps):
     gbs = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "launch_ms": round(launch_ms, 5)}
+            "launch_ms": round(launch_ms, 5), "launches": int(st.step_launches)}
 
 
 def cpu_baseline(p, seconds_target=15.0):
@@ -142,6 +169,52 @@ def parity_check(qew):
     return res
 
 
+def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
+    """Markdown summary of rocprofv3 CSV output of a bench.py run (kernel trace
+    and/or FETCH_SIZE / WRITE_SIZE / SQ counters), for profiles/."""
+    import csv
+    import glob
+    import statistics
+
+    def rows(pattern):
+        out = []
+        for fn in glob.glob(os.path.join(run_dir, "**", pattern), recursive=True):
+            out += list(csv.DictReader(open(fn)))
+        return out
+
+    def short(n):
+        return n.split("(")[0].replace("void ", "")
+
+    lines = []
+    stats = rows("*kernel_stats.csv")
+    if stats:
+        lines += ["| kernel | calls | total ms | average us |", "|---|---|---|---|"]
+        for r in stats[:8]:
+            lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} "
+                         f"| {float(r['AverageNs']) / 1e3:.1f} |")
+    trace = rows("*kernel_trace.csv")
+    if trace:
+        trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+        for init, tag in (("k_init_split", "k_step_fused"), ("k_init_plain", "k_step_plain")):
+            idx = [i for i, r in enumerate(trace) if init in r["Kernel_Name"]]
+            if not idx:
+                continue
+            seg = [r for r in trace[idx[-1]:] if tag in r["Kernel_Name"]]
+            if seg:
+                d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in seg]
+                lines.append(f"\ntimed run: `{short(seg[0]['Kernel_Name'])}` {len(seg)} launches, "
+                             f"average {sum(d) / len(d):.5f} ms")
+    counters = rows("*counter_collection.csv")
+    if counters:
+        per = {}
+        for r in counters:
+            per.setdefault((short(r["Kernel_Name"]), r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        lines += ["", "| kernel | counter | dispatches | median per dispatch |", "|---|---|---|---|"]
+        for (k, c), v in sorted(per.items()):
+            lines.append(f"| `{k}` | {c} | {len(v)} | {statistics.median(v):.6g} |")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,7 +229,17 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="print a markdown summary of rocprofv3 CSV output under DIR and exit")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+
+    if args.summarize_profile:
+        print(summarize_profile(args.summarize_profile))
+        return
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "

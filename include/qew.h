@@ -157,6 +157,21 @@ qew_status qew_autotune(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *str
 qew_status qew_run(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *stream, int32_t resume,
                    double *h_v, double *h_w2, double *h_ubar);
 
+/*
+ * Disorder average (the overbar of Sec. II, Eqs. (3)-(5)) of the series held
+ * in the workspace, computed on the device in FP64 with equal weight per
+ * sample, for every measurement taken so far.  h_out is a host array
+ * [7][n_meas], row by row:
+ *   0 mean_s v_s, 1 its standard error, 2 mean_s w2_s, 3 its standard error,
+ *   4 mean_s ubar_s, 5 its standard error,
+ *   6 mean_s w2_s + Var_s(ubar_s): the width about the ensemble centre of mass
+ *     (the literal reading of Eq. (5) with u(t) of Eq. (4) inside the square).
+ * Standard error = sample standard deviation / sqrt(S) (0 when S = 1);
+ * Var_s is the population variance over samples.  Entries of measurements
+ * not yet taken are NaN.  Synchronous.
+ */
+qew_status qew_ensemble(const qew_plan_t *plan, const void *d_ws, void *stream, double *h_out);
+
 /* Statistics of the last qew_run of this plan (host pointer). */
 qew_status qew_run_stats_get(const qew_plan_t *plan, qew_run_stats *stats);
 

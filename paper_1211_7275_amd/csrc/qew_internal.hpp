@@ -65,6 +65,9 @@ hipError_t launch_meas_split(const Tables& t, SplitBuf b, const Phys& ph, int ki
                              hipStream_t st);
 hipError_t launch_meas_final(const Tables& t, int n_samples, const Partial* part, int meas_index,
                              int n_meas, double* series, hipStream_t st);
+hipError_t launch_ensemble(int n_samples, int n_meas, const double* series, double* out,
+                           hipStream_t st);
+hipError_t launch_fill_f64(double* p, int64_t n, double value, hipStream_t st);
 hipError_t launch_philox_fill(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                               int64_t n, hipStream_t st);
 hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int precision,

@@ -550,6 +550,51 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Disorder average over samples of one measurement index per workgroup:
+// two passes (mean, then squared deviations) in a fixed order.
+__device__ __forceinline__ double block_sum1(double v, double* lds) {
+  v = wave_sum_f64(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < kBlock / 64; ++i) s += lds[i];
+  __syncthreads();
+  return s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_ensemble(int S, int n_meas, const double* __restrict__ series, double* __restrict__ out) {
+  __shared__ double lds[kBlock / 64];
+  const int mi = blockIdx.x;
+  double mean[3], m2[3];
+  for (int q = 0; q < 3; ++q) {
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < S; s += kBlock) acc += series[((int64_t)s * n_meas + mi) * 3 + q];
+    mean[q] = block_sum1(acc, lds) / (double)S;
+    double dev = 0.0;
+    for (int s = threadIdx.x; s < S; s += kBlock) {
+      const double e = series[((int64_t)s * n_meas + mi) * 3 + q] - mean[q];
+      dev += e * e;
+    }
+    m2[q] = block_sum1(dev, lds);
+  }
+  if (threadIdx.x == 0) {
+    // series layout per sample: {v, ubar, w2}; output rows: v, se, w2, se, ubar, se, w2 about ensemble ubar
+    const int src[3] = {0, 2, 1};
+    for (int r = 0; r < 3; ++r) {
+      const int q = src[r];
+      out[(2 * r) * n_meas + mi] = mean[q];
+      out[(2 * r + 1) * n_meas + mi] = S > 1 ? sqrt(m2[q] / (double)(S - 1) / (double)S) : 0.0;
+    }
+    out[6 * n_meas + mi] = mean[2] + m2[1] / (double)S;
+  }
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double value) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
 // ---------------------------------------------------------------------------
 // Debug kernels.
 // ---------------------------------------------------------------------------
@@ -690,6 +735,20 @@ hipError_t launch_meas_final(const Tables& t, int n_samples, const Partial* part
                              int n_meas, double* series, hipStream_t st) {
   hipLaunchKernelGGL(k_meas_final, dim3(n_samples), dim3(kBlock), 0, st, t, part, meas_index, n_meas,
                      series);
+  return hipGetLastError();
+}
+
+hipError_t launch_ensemble(int n_samples, int n_meas, const double* series, double* out,
+                           hipStream_t st) {
+  if (n_meas <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ensemble, dim3(n_meas), dim3(kBlock), 0, st, n_samples, n_meas, series, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((uint32_t)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, p, n,
+                     value);
   return hipGetLastError();
 }
 

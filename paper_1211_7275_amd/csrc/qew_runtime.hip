@@ -54,7 +54,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
   size_t off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len;
   size_t tables_end;
-  size_t part, series, stA0, stA1, stB0, stB1, ndA, ndB;
+  size_t part, series, ens, stA0, stA1, stB0, stB1, ndA, ndB;
   size_t total;
 };
 
@@ -148,6 +148,7 @@ void compute_layout(qew_plan_t* p) {
   l.tables_end = o;
   l.part = take(nmt * sizeof(Partial));
   l.series = take(S * std::max<size_t>(p->meas.size(), 1) * 3 * 8);
+  l.ens = take(7 * std::max<size_t>(p->meas.size(), 1) * 8);
   const size_t n = (size_t)p->padded;
   if (p->precision == QEW_FP64_PLAIN) {
     l.stA0 = take(n * 8);
@@ -252,8 +253,21 @@ qew_status upload_tables(qew_plan_t* p, void* ws, hipStream_t st) {
   return QEW_OK;
 }
 
+double* series_of(const qew_plan_t* p, void* ws) {
+  return reinterpret_cast<double*>(static_cast<char*>(ws) + p->lay.series);
+}
+
+// Measurements not yet taken read as NaN.
+qew_status clear_series(const qew_plan_t* p, void* ws, hipStream_t st) {
+  QEW_HIP(launch_fill_f64(series_of(p, ws), (int64_t)p->S * (int64_t)p->meas.size() * 3,
+                          __builtin_nan(""), st));
+  return QEW_OK;
+}
+
 qew_status init_state(qew_plan_t* p, void* ws, hipStream_t st) {
   const Tables t = tables_of(p, ws);
+  qew_status rc = clear_series(p, ws, st);
+  if (rc != QEW_OK) return rc;
   if (p->precision == QEW_FP64_PLAIN) {
     QEW_HIP(launch_init_plain(t, plain_buf(p, ws, 0), st));
   } else {
@@ -684,6 +698,21 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   return QEW_OK;
 }
 
+qew_status qew_ensemble(const qew_plan_t* p, const void* ws, void* stream, double* h_out) {
+  g_err.clear();
+  if (!p || !ws || !h_out) return fail(QEW_EINVAL, "plan, workspace and h_out must be non-NULL");
+  if (p->state_ws != ws) return fail(QEW_EINVAL, "this workspace holds no run of this plan");
+  const int n_meas = (int)p->meas.size();
+  if (n_meas == 0) return QEW_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void* w = const_cast<void*>(ws);
+  double* ens = reinterpret_cast<double*>(static_cast<char*>(w) + p->lay.ens);
+  QEW_HIP(launch_ensemble(p->S, n_meas, series_of(p, w), ens, st));
+  QEW_HIP(hipMemcpyAsync(h_out, ens, (size_t)7 * n_meas * 8, hipMemcpyDeviceToHost, st));
+  QEW_HIP(hipStreamSynchronize(st));
+  return QEW_OK;
+}
+
 qew_status qew_read_state(const qew_plan_t* p, const void* ws, void* stream, int32_t s, double* h_u,
                           int64_t* h_step) {
   g_err.clear();
@@ -720,7 +749,11 @@ qew_status qew_write_state(qew_plan_t* p, void* ws, void* stream, int32_t s, con
   for (int64_t j = 0; j < L; ++j)
     if (!std::isfinite(h_u[j]) || std::fabs(h_u[j]) > 1e9) return fail(QEW_EINVAL, "h_u[%lld] not finite or beyond 1e9", (long long)j);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (p->state_ws != ws) p->cur_buf = 0;
+  if (p->state_ws != ws) {
+    p->cur_buf = 0;
+    qew_status rc = clear_series(p, ws, st);
+    if (rc != QEW_OK) return rc;
+  }
   if (p->precision == QEW_FP64_PLAIN) {
     QEW_HIP(hipMemcpyAsync(plain_buf(p, ws, p->cur_buf) + p->off[s], h_u, L * 8, hipMemcpyHostToDevice, st));
     QEW_HIP(hipStreamSynchronize(st));

@@ -31,8 +31,10 @@ QEW_FLAG_NO_GRAPH = 1
 QEW_FLAG_TIMING = 2
 
 EXPORTS = ("qew_plan", "qew_workspace_bytes", "qew_plan_info_get", "qew_autotune", "qew_run",
-           "qew_run_stats_get", "qew_read_state", "qew_write_state", "qew_debug_philox_fill",
-           "qew_debug_force_eval", "qew_plan_destroy", "qew_last_error")
+           "qew_ensemble", "qew_run_stats_get", "qew_read_state", "qew_write_state",
+           "qew_debug_philox_fill", "qew_debug_force_eval", "qew_plan_destroy", "qew_last_error")
+
+ENSEMBLE_ROWS = ("v", "v_se", "w2", "w2_se", "ubar", "ubar_se", "w2_about_ensemble_ubar")
 
 
 class qew_problem(ctypes.Structure):
@@ -81,6 +83,8 @@ def _load():
     lib.qew_autotune.restype = st
     lib.qew_run.argtypes = [vp, vp, sz, vp, ctypes.c_int32, dp, dp, dp]
     lib.qew_run.restype = st
+    lib.qew_ensemble.argtypes = [vp, vp, vp, dp]
+    lib.qew_ensemble.restype = st
     lib.qew_run_stats_get.argtypes = [vp, ctypes.POINTER(qew_run_stats)]
     lib.qew_run_stats_get.restype = st
     lib.qew_read_state.argtypes = [vp, vp, vp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64)]
@@ -148,6 +152,13 @@ def qew_autotune(plan, ws, stream=None):
 def qew_run(plan, ws, stream, resume, h_v, h_w2, h_ubar):
     _check(_lib.qew_run(plan, ws.data_ptr(), ws.numel(), _stream_ptr(stream), int(resume),
                         _dptr(h_v), _dptr(h_w2), _dptr(h_ubar)), "qew_run")
+
+
+def qew_ensemble(plan, ws, n_meas, stream=None):
+    """Disorder averages on the device: dict of ENSEMBLE_ROWS -> [n_meas] arrays."""
+    out = np.zeros((7, int(n_meas)), np.float64)
+    _check(_lib.qew_ensemble(plan, ws.data_ptr(), _stream_ptr(stream), _dptr(out)), "qew_ensemble")
+    return dict(zip(ENSEMBLE_ROWS, out))
 
 
 def qew_run_stats_get(plan):
@@ -266,6 +277,10 @@ class Simulation:
         ub = np.full_like(v, np.nan)
         qew_run(self.plan, self.ws, stream, resume, v, w2, ub)
         return {"v": v, "w2": w2, "ubar": ub}
+
+    def ensemble(self, stream=None):
+        """Disorder average and standard errors of the series (computed on the device)."""
+        return qew_ensemble(self.plan, self.ws, self.n_meas, stream)
 
     def stats(self):
         return qew_run_stats_get(self.plan)

@@ -152,6 +152,30 @@ def test_config0_fp32_split_parity(qew, c0_oracle, path):
     assert rel_err(out["ubar"], ref["ubar"], floor=1.0) <= 1e-3
 
 
+def test_ensemble_on_device(qew, c0_oracle):
+    """Disorder average (overbar of Eqs. (3)-(5)) computed by the library: equal
+    weight per sample, standard errors, and the width about the ensemble ubar."""
+    p, ref = c0_oracle
+    S = len(p["L"])
+    for prec, path in ((qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP), (qew.QEW_FP32_SPLIT, qew.QEW_FUSED)):
+        say("ensemble", prec, path)
+        sim = qew.Simulation(p, precision=prec, path=path)
+        try:
+            out = sim.run()
+            ens = sim.ensemble()
+        finally:
+            sim.close()
+        for key in ("v", "w2", "ubar"):
+            assert np.allclose(ens[key], out[key].mean(0), rtol=1e-14, atol=0)
+            se = out[key].std(0, ddof=1) / np.sqrt(S)
+            assert np.allclose(ens[key + "_se"], se, rtol=1e-9, atol=1e-300)
+        wg = out["w2"].mean(0) + out["ubar"].var(0)
+        assert np.allclose(ens["w2_about_ensemble_ubar"], wg, rtol=1e-12, atol=0)
+        tol = 1e-10 if prec == qew.QEW_FP64_PLAIN else 1e-3
+        assert rel_err(ens["v"], ref["v"].mean(0)) <= tol
+        assert rel_err(ens["w2"], ref["w2"].mean(0)) <= tol
+
+
 # -------------------------------------------- fused == one-step (bitwise) --
 
 GEOMS = [(1, 1024), (5, 1024), (8, 1024), (16, 2048), (32, 2048), (32, 4096), (64, 4096)]
@@ -321,12 +345,15 @@ def test_resume_bit_identical(qew, mode):
         for s in range(2):
             sim.write_state(s, half["u"][s], H)
         rest = sim.run(resume=True)
+        ens = sim.ensemble()
         u_rest = [sim.read_state(s)[0] for s in range(2)]
     finally:
         sim.close()
     for s in range(2):
         assert np.array_equal(u_rest[s], full["u"][s])
+    # measurements before the restored step were never taken in this workspace
     sel = meas >= H
+    assert np.all(np.isnan(ens["v"][~sel])) and np.all(np.isfinite(ens["v"][sel]))
     for key in ("v", "ubar", "w2"):
         assert np.array_equal(rest[key][:, sel], full[key][:, sel])
 
