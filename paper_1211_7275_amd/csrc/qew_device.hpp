@@ -106,30 +106,35 @@ __device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, u
 }
 
 // ---------------------------------------------------------------------------
-// Catmull-Rom spline through p0..p3 at nodes -1, 0, 1, 2, at s in [0, 1).
-// FP32 form: value = p1 + s (a1 + s (a2 + s a3)) with
+// Catmull-Rom spline through p0..p3 at nodes -1, 0, 1, 2, at s in [0, 1].
+// value(s) = p1 + s (a1 + s (a2 + s a3)),  slope(s) = a1 + s (2 a2 + 3 a3 s),
 //   a1 = (p2 - p0) / 2, a2 = p0 - 5/2 p1 + 2 p2 - 1/2 p3,
-//   a3 = 3/2 (p1 - p2) + 1/2 (p3 - p0);  slope = a1 + s (2 a2 + 3 a3 s).
-// RF uses the value, RB the slope (F_p = -dU/du).  The coefficients of a
-// cell are computed once (spline_coef) and evaluated every step
-// (spline_eval); every kernel goes through these two functions, so a cached
-// coefficient set gives exactly the force a fresh evaluation gives.
-//   RF: {x, y, z, w} = {p1, a1, a2, a3}
-//   RB: {x, y, z, w} = {0, a1, 2 a2, 3 a3}
+//   a3 = 3/2 (p1 - p2) + 1/2 (p3 - p0).
+// RF uses the value, RB the slope (F_p = -dU/du).
+//
+// spline_coef returns the polynomial in s of  f + g * (value or slope),  with
+// g = +strength (RF) or -strength (RB) and f the drive, so one Horner
+// evaluation (spline_eval) gives the drive plus the pinning force:
+//   RF: {x, y, z, w} = {f + g p1, g a1, g a2, g a3}         (cubic)
+//   RB: {x, y, z, w} = {f + g a1, g 2 a2, g 3 a3, unused}   (quadratic)
+// The coefficients of a cell are computed once and evaluated every step;
+// every kernel goes through these two functions, so a cached coefficient set
+// gives exactly the force a fresh evaluation gives.
 // ---------------------------------------------------------------------------
 template <int KIND>
-__device__ __forceinline__ float4 spline_coef(float p0, float p1, float p2, float p3) {
+__device__ __forceinline__ float4 spline_coef(float p0, float p1, float p2, float p3, float g,
+                                              float f) {
   const float a1 = 0.5f * (p2 - p0);
   const float d30 = p3 - p0;
   const float d12 = p1 - p2;
   if constexpr (KIND == kRF) {
     const float a2 = fmaf(-0.5f, p3, fmaf(2.0f, p2, fmaf(-2.5f, p1, p0)));
     const float a3 = fmaf(1.5f, d12, 0.5f * d30);
-    return make_float4(p1, a1, a2, a3);
+    return make_float4(fmaf(g, p1, f), g * a1, g * a2, g * a3);
   } else {
     const float b2 = fmaf(-1.0f, p3, fmaf(4.0f, p2, fmaf(-5.0f, p1, 2.0f * p0)));
     const float b3 = fmaf(4.5f, d12, 1.5f * d30);
-    return make_float4(0.0f, a1, b2, b3);
+    return make_float4(fmaf(g, a1, f), g * b2, g * b3, 0.0f);
   }
 }
 
@@ -138,13 +143,8 @@ __device__ __forceinline__ float spline_eval(const float4& a, float s) {
   if constexpr (KIND == kRF) {
     return fmaf(s, fmaf(s, fmaf(s, a.w, a.z), a.y), a.x);
   } else {
-    return fmaf(s, fmaf(s, a.w, a.z), a.y);
+    return fmaf(s, fmaf(s, a.z, a.y), a.x);
   }
-}
-
-template <int KIND>
-__device__ __forceinline__ float spline_f32(float p0, float p1, float p2, float p3, float s) {
-  return spline_eval<KIND>(spline_coef<KIND>(p0, p1, p2, p3), s);
 }
 
 // FP64 form, same operation order as the textbook polynomial
@@ -172,30 +172,26 @@ struct SplitPhys {
 };
 
 // Total force of Eq. (1) on a split site (cell c, offset r) with neighbours
-// (cl, rl), (cr, rr) and spline coefficients `a` of its cell.  The integer
-// part of the Laplacian is exact; the offsets carry the fraction.
+// (cl, rl), (cr, rr); `a` holds the coefficients of f + F_p of its cell.  The
+// integer part of the Laplacian is exact; the offsets carry the fraction
+// ((rl + rr) - 2 r rounded once: 2 r is exact).
 template <int KIND>
 __device__ __forceinline__ float split_force(int32_t c, float r, int32_t cl, float rl, int32_t cr,
-                                             float rr, const float4& a, float f,
-                                             const SplitPhys& ph) {
-  // (rl + rr) - 2 r rounded once (2 r is exact), written as one FMA.
-  const float lap = (float)((cl - c) + (cr - c)) + fmaf(-2.0f, r, rl + rr);
-  const float sp = spline_eval<KIND>(a, r);
-  return fmaf(ph.c, lap, fmaf(ph.sgn_str, sp, f));
+                                             float rr, const float4& a, float cel) {
+  const float lap = (float)((cr - c) - (c - cl)) + fmaf(-2.0f, r, rl + rr);
+  return fmaf(cel, lap, spline_eval<KIND>(a, r));
 }
 
-// Euler update of a split site: r' = r + dt F, then move whole units into the cell.
-__device__ __forceinline__ void split_advance(int32_t& c, float& r, float F, float dt) {
+// Euler update of a split site: r' = r + dt F, then whole units move into the
+// cell.  The offset stays in [0, 1]: it reaches exactly 1 only when r + dt F
+// is a negative number above -2^-25 (r' = 1 - |r + dt F| rounds to 1); the
+// site then sits at the right end of its cell, where the spline equals the
+// next cell's left end.
+__device__ __forceinline__ float split_advance(float& r, float F, float dt) {
   const float rn = fmaf(dt, F, r);
   const float fl = floorf(rn);
-  float rr = rn - fl;
-  int32_t cc = c + (int32_t)fl;
-  if (rr >= 1.0f) {  // rn a tiny negative: rn + 1 rounds to 1
-    rr -= 1.0f;
-    cc += 1;
-  }
-  c = cc;
-  r = rr;
+  r = rn - fl;
+  return fl;  // cells moved
 }
 
 struct PlainPhys {

@@ -22,6 +22,7 @@ struct Tables {
   const int32_t* ft_len;    //        valid sites
   int32_t n_mt;
   int32_t n_ft;
+  int* err;                 // error flags raised by kernels (bit 0: tile cell span >= 2^23)
 };
 
 struct SplitBuf {
@@ -68,6 +69,7 @@ hipError_t launch_meas_final(const Tables& t, int n_samples, const Partial* part
 hipError_t launch_ensemble(int n_samples, int n_meas, const double* series, double* out,
                            hipStream_t st);
 hipError_t launch_fill_f64(double* p, int64_t n, double value, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int64_t n, int value, hipStream_t st);
 hipError_t launch_philox_fill(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                               int64_t n, hipStream_t st);
 hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int precision,

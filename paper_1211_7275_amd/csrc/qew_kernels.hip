@@ -163,10 +163,10 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
     float r = in.frac[base + j];
     float n0, n1, n2, n3;
     nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
-    const float4 a = spline_coef<KIND>(n0, n1, n2, n3);
+    const float4 a = spline_coef<KIND>(n0, n1, n2, n3, sp.sgn_str, f);
     const float F = split_force<KIND>(c, r, in.cell[base + jm], in.frac[base + jm],
-                                      in.cell[base + jp], in.frac[base + jp], a, f, sp);
-    split_advance(c, r, F, sp.dt);
+                                      in.cell[base + jp], in.frac[base + jp], a, sp.c);
+    c += (int32_t)split_advance(r, F, sp.dt);
     out.cell[base + j] = c;
     out.frac[base + j] = r;
   }
@@ -177,9 +177,11 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 //
 // One workgroup owns one tile of T = 256 P consecutive sites of one sample at
 // a time: positions p0 - halo .. p0 - halo + T - 1 (periodic in the sample).
-// Thread t holds sites t P .. t P + P - 1 in registers: cell, offset and the
-// spline coefficients of the current cell.  The four raw nodes of every site
-// live in LDS, slot-major (node index i * 256 + t).  Each sub-step:
+// Thread t holds sites t P .. t P + P - 1 in registers: the cell as an exact
+// float relative to the tile's first cell (no int/float conversion per step),
+// the offset, and the coefficients of f + F_p of the current cell.  The four
+// raw nodes of every site live in LDS, slot-major (node index i * 256 + t).
+// Each sub-step:
 //   1. every site takes one Euler step (neighbours within a thread directly,
 //      across lanes by wave shuffles, across waves through LDS);
 //   2. a site whose cell changed posts a request (its LDS node index, new
@@ -192,10 +194,10 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 // A sub-step with no request at all skips 3-4.  After nsub <= halo
 // sub-steps the sites within `halo` of either tile end hold garbage (the tile
 // ends reflect), and the valid part [halo, halo + len) is written back with
-// its nodes.
+// its nodes.  Every value equals what the one-step kernel computes: the
+// float cell differences are exact integers (checked: a tile whose cells
+// spread over 2^23 or more raises the error flag).
 // ---------------------------------------------------------------------------
-// Request slots per wave and sub-step (more requests are served in extra
-// rounds), and the occupancy target (waves per SIMD) of the fused kernel.
 #ifndef QEW_REQ_PER_WAVE
 #define QEW_REQ_PER_WAVE 64
 #endif
@@ -203,6 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 #define QEW_FUSED_MIN_WAVES 4
 #endif
 constexpr int kReqPerWave = QEW_REQ_PER_WAVE;
+constexpr float kCellSpan = 8388608.0f;  // 2^23
 
 template <int KIND, int P>
 __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
@@ -213,12 +216,12 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
   __shared__ float4 s_nodes[T];
   __shared__ int4 s_req[NW * RQ];
   __shared__ int s_count[2][NW];
-  __shared__ int2 s_edge[2][NW][2];
+  __shared__ float2 s_edge[2][NW][2];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = uniform_i32(tid >> 6);
-  const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
+  const float cel = ph.cf, dt = ph.dtf, g = ph.sgn_strf;
 
   for (int ti = blockIdx.x; ti < t.n_ft; ti += gridDim.x) {
     const int s = uniform_i32(t.ft_s[ti]);
@@ -232,53 +235,63 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
     int start_mod = start % L;
     if (start_mod < 0) start_mod += L;
     const bool contiguous = start >= 0 && start + T <= L && (start & 3) == 0;
+    const int32_t cbase = uniform_i32(in.cell[base + start_mod]);
 
-    int32_t c[P];
+    float c[P];  // cell - cbase, an exact integer
     float r[P];
     float4 a[P];
+    bool far = false;
     if (contiguous) {
-      const int64_t g = base + start + tid * P;
+      const int64_t gi = base + start + tid * P;
 #pragma unroll
       for (int v = 0; v < P / 4; ++v) {
-        const int4 cv = *reinterpret_cast<const int4*>(in.cell + g + 4 * v);
-        const float4 rv = *reinterpret_cast<const float4*>(in.frac + g + 4 * v);
-        c[4 * v] = cv.x; c[4 * v + 1] = cv.y; c[4 * v + 2] = cv.z; c[4 * v + 3] = cv.w;
+        const int4 cv = *reinterpret_cast<const int4*>(in.cell + gi + 4 * v);
+        const float4 rv = *reinterpret_cast<const float4*>(in.frac + gi + 4 * v);
+        const int32_t cc[4] = {cv.x - cbase, cv.y - cbase, cv.z - cbase, cv.w - cbase};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          far |= (uint32_t)(cc[e] + (1 << 23)) >= (1u << 24);
+          c[4 * v + e] = (float)cc[e];
+        }
         r[4 * v] = rv.x; r[4 * v + 1] = rv.y; r[4 * v + 2] = rv.z; r[4 * v + 3] = rv.w;
       }
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        const float4 nd = in.nodes[g + i];
+        const float4 nd = in.nodes[gi + i];
         s_nodes[i * kBlock + tid] = nd;
-        a[i] = spline_coef<KIND>(nd.x, nd.y, nd.z, nd.w);
+        a[i] = spline_coef<KIND>(nd.x, nd.y, nd.z, nd.w, g, f);
       }
     } else {
       int pos = (start_mod + tid * P) % L;
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        c[i] = in.cell[base + pos];
+        const int32_t cc = in.cell[base + pos] - cbase;
+        far |= (uint32_t)(cc + (1 << 23)) >= (1u << 24);
+        c[i] = (float)cc;
         r[i] = in.frac[base + pos];
         const float4 nd = in.nodes[base + pos];
         s_nodes[i * kBlock + tid] = nd;
-        a[i] = spline_coef<KIND>(nd.x, nd.y, nd.z, nd.w);
+        a[i] = spline_coef<KIND>(nd.x, nd.y, nd.z, nd.w, g, f);
         pos = (pos + 1 == L) ? 0 : pos + 1;
       }
     }
-    if (lane == 0) s_edge[0][wv][0] = make_int2(c[0], __float_as_int(r[0]));
-    if (lane == 63) s_edge[0][wv][1] = make_int2(c[P - 1], __float_as_int(r[P - 1]));
+    if (__ballot(far) && lane == 0) atomicOr(t.err, 1);
+    if (lane == 0) s_edge[0][wv][0] = make_float2(c[0], r[0]);
+    if (lane == 63) s_edge[0][wv][1] = make_float2(c[P - 1], r[P - 1]);
     __syncthreads();
 
     for (int sub = 0; sub < nsub; ++sub) {
       const int par = sub & 1;
       // Neighbours of this thread's end sites.  The tile ends reflect.
-      int32_t cle = __shfl_up(c[P - 1], 1, 64);
+      float cle = __shfl_up(c[P - 1], 1, 64);
       float rle = __shfl_up(r[P - 1], 1, 64);
-      int32_t cre = __shfl_down(c[0], 1, 64);
+      float cre = __shfl_down(c[0], 1, 64);
       float rre = __shfl_down(r[0], 1, 64);
       if (lane == 0) {
         if (wv > 0) {
-          const int2 e = s_edge[par][wv - 1][1];
+          const float2 e = s_edge[par][wv - 1][1];
           cle = e.x;
-          rle = __int_as_float(e.y);
+          rle = e.y;
         } else {
           cle = c[0];
           rle = r[0];
@@ -286,41 +299,46 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
       }
       if (lane == 63) {
         if (wv < NW - 1) {
-          const int2 e = s_edge[par][wv + 1][0];
+          const float2 e = s_edge[par][wv + 1][0];
           cre = e.x;
-          rre = __int_as_float(e.y);
+          rre = e.y;
         } else {
           cre = c[P - 1];
           rre = r[P - 1];
         }
       }
 
-      // Euler step of every site; a site that changed cell posts a request.
+      // Euler step of every site (Jacobi: old values of the neighbours); a
+      // site that changed cell posts a request.
       uint64_t moved[P];
       uint32_t nreq = 0u;  // wave-uniform
-      int32_t pc = cle;
+      float dl = c[0] - cle;  // cell difference to the left neighbour
       float pr = rle;
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        const int32_t nc = (i + 1 < P) ? c[i + 1] : cre;
+        const float nc = (i + 1 < P) ? c[i + 1] : cre;
         const float nr = (i + 1 < P) ? r[i + 1] : rre;
-        const float F = split_force<KIND>(c[i], r[i], pc, pr, nc, nr, a[i], f, sp);
-        const int32_t oc = c[i];
-        pc = oc;
+        const float dr = nc - c[i];
+        const float lap = (dr - dl) + fmaf(-2.0f, r[i], pr + nr);
+        const float F = fmaf(cel, lap, spline_eval<KIND>(a[i], r[i]));
+        dl = dr;
         pr = r[i];
-        split_advance(c[i], r[i], F, sp.dt);
-        moved[i] = __ballot(c[i] != oc);
-        if (c[i] != oc) {
+        const float oc = c[i];
+        const float fl = split_advance(r[i], F, dt);
+        c[i] = oc + fl;
+        moved[i] = __ballot(fl != 0.0f);
+        if (fl != 0.0f) {
           const uint32_t k = nreq + mbcnt64(moved[i]);
-          if (k < (uint32_t)RQ) s_req[wv * RQ + k] = make_int4(i * kBlock + tid, c[i], oc, 0);
+          if (k < (uint32_t)RQ)
+            s_req[wv * RQ + k] = make_int4(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc), 0);
         }
         nreq += (uint32_t)__popcll(moved[i]);
       }
       if (lane == 0) {
-        s_edge[par ^ 1][wv][0] = make_int2(c[0], __float_as_int(r[0]));
+        s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
         s_count[par][wv] = (int)nreq;
       }
-      if (lane == 63) s_edge[par ^ 1][wv][1] = make_int2(c[P - 1], __float_as_int(r[P - 1]));
+      if (lane == 63) s_edge[par ^ 1][wv][1] = make_float2(c[P - 1], r[P - 1]);
       __syncthreads();
 
       int cnt[NW];
@@ -339,9 +357,9 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
           for (int i = 0; i < P; ++i) {
             if ((moved[i] >> lane) & 1u) {
               const uint32_t k = n + mbcnt64(moved[i]);
-              if (k >= lo && k < lo + RQ) {  // served by full regeneration of the window
-                s_req[wv * RQ + (k - lo)] = make_int4(i * kBlock + tid, c[i], c[i], 0);
-              }
+              if (k >= lo && k < lo + RQ)  // served by full regeneration of the window
+                s_req[wv * RQ + (k - lo)] =
+                    make_int4(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(c[i]), 0);
             }
             n += (uint32_t)__popcll(moved[i]);
           }
@@ -361,18 +379,19 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
 #pragma unroll
           for (int x = 1; x < NW; ++x) w += (q >= pre[x]) ? 1 : 0;
           const int slot = w * RQ + (q - pre[w]);
-          const int4 rq = s_req[slot];  // {node index, new cell, old cell}
+          const int4 rq = s_req[slot];  // {node index, new cell, old cell} (cells relative to cbase)
           const int ni = rq.x;
-          const int32_t cell = rq.y;
-          const int32_t move = rq.y - rq.z;  // +1, -1, or anything else: regenerate all four
+          const float cnew = __int_as_float(rq.y);
+          const float move = cnew - __int_as_float(rq.z);
+          const int32_t cell = cbase + (int32_t)cnew;
           const int lp = (ni % kBlock) * P + ni / kBlock;  // tile-local position
           int j = start_mod + lp;
           if (j >= L) j -= L;
           if (j >= L) j %= L;
           float4 w4 = s_nodes[ni];
-          if (move == 1) {
+          if (move == 1.0f) {
             w4 = make_float4(w4.y, w4.z, w4.w, node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
-          } else if (move == -1) {
+          } else if (move == -1.0f) {
             w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1), w4.x, w4.y, w4.z);
           } else {
             w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1),
@@ -381,7 +400,7 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
                              node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
           }
           s_nodes[ni] = w4;
-          const float4 co = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w);
+          const float4 co = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w, g, f);
           s_req[slot] = make_int4(__float_as_int(co.x), __float_as_int(co.y), __float_as_int(co.z),
                                   __float_as_int(co.w));
         }
@@ -412,7 +431,8 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
 #pragma unroll
       for (int v = 0; v < P / 4; ++v) {
         *reinterpret_cast<int4*>(out.cell + g0 + 4 * v) =
-            make_int4(c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]);
+            make_int4(cbase + (int32_t)c[4 * v], cbase + (int32_t)c[4 * v + 1],
+                      cbase + (int32_t)c[4 * v + 2], cbase + (int32_t)c[4 * v + 3]);
         *reinterpret_cast<float4*>(out.frac + g0 + 4 * v) =
             make_float4(r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
       }
@@ -423,10 +443,10 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
       for (int i = 0; i < P; ++i) {
         const int q = qb + i;
         if (q >= halo && q < halo + len) {
-          const int64_t g = base + p0 + (q - halo);
-          out.cell[g] = c[i];
-          out.frac[g] = r[i];
-          out.nodes[g] = s_nodes[i * kBlock + tid];
+          const int64_t gi = base + p0 + (q - halo);
+          out.cell[gi] = cbase + (int32_t)c[i];
+          out.frac[gi] = r[i];
+          out.nodes[gi] = s_nodes[i * kBlock + tid];
         }
       }
     }
@@ -487,9 +507,9 @@ __global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phy
     const float r = b.frac[base + j];
     float n0, n1, n2, n3;
     nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
-    const float4 a = spline_coef<KIND>(n0, n1, n2, n3);
+    const float4 a = spline_coef<KIND>(n0, n1, n2, n3, sp.sgn_str, f);
     const float F = split_force<KIND>(c, r, b.cell[base + jm], b.frac[base + jm], b.cell[base + jp],
-                                      b.frac[base + jp], a, f, sp);
+                                      b.frac[base + jp], a, sp.c);
     sf += (double)F;
     const double x = (double)(c - Kc) + ((double)r - Kr);  // exact
     s1 += x;
@@ -590,6 +610,11 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+__global__ void k_fill_i32(int* p, int64_t n, int value) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
 __global__ void k_fill_f64(double* p, int64_t n, double value) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = value;
@@ -634,7 +659,7 @@ __global__ void __launch_bounds__(kBlock)
     const float p2 = node_f32<KIND>(j, c + 1, id, k0, k1);
     const float p3 = node_f32<KIND>(j, c + 2, id, k0, k1);
     const float sg = (KIND == kRF) ? (float)strength : -(float)strength;
-    out[i] = (double)(sg * spline_f32<KIND>(p0, p1, p2, p3, r));
+    out[i] = (double)spline_eval<KIND>(spline_coef<KIND>(p0, p1, p2, p3, sg, 0.0f), r);
   }
 }
 
@@ -742,6 +767,13 @@ hipError_t launch_ensemble(int n_samples, int n_meas, const double* series, doub
                            hipStream_t st) {
   if (n_meas <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ensemble, dim3(n_meas), dim3(kBlock), 0, st, n_samples, n_meas, series, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int64_t n, int value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((uint32_t)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, p, n,
+                     value);
   return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ constexpr int kTuneK[3] = {8, 16, 32};
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len;
+  size_t err, off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len;
   size_t tables_end;
   size_t part, series, ens, stA0, stA1, stB0, stB1, ndA, ndB;
   size_t total;
@@ -133,6 +133,7 @@ void compute_layout(qew_plan_t* p) {
     o = align256(o + bytes);
     return at;
   };
+  l.err = take(4);
   l.off = take(S * 8);
   l.L = take(S * 4);
   l.f = take(S * 8);
@@ -188,6 +189,7 @@ Tables tables_of(const qew_plan_t* p, void* ws) {
   t.ft_len = reinterpret_cast<const int32_t*>(b + l.ft_len);
   t.n_mt = (int32_t)p->mt_s.size();
   t.n_ft = (int32_t)p->ft_s.size();
+  t.err = reinterpret_cast<int*>(b + l.err);
   return t;
 }
 
@@ -601,6 +603,7 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   }
   p->stats = qew_run_stats{};
   if ((rc = upload_tables(p, ws, st)) != QEW_OK) return rc;
+  QEW_HIP(launch_fill_i32(tables_of(p, ws).err, 1, 0, st));
   if ((rc = ensure_fused_grid(p)) != QEW_OK) return rc;
   if (!resume) {
     if ((rc = init_state(p, ws, st)) != QEW_OK) return rc;
@@ -663,16 +666,26 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
     return rc;
   }
   std::vector<double> series;
+  int err_flags = 0;
   if (n_meas > mi0) {
     series.resize((size_t)p->S * n_meas * 3);
     he = hipMemcpyAsync(series.data(), static_cast<char*>(ws) + p->lay.series, series.size() * 8,
                         hipMemcpyDeviceToHost, st);
   }
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(&err_flags, static_cast<char*>(ws) + p->lay.err, 4, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) {
     cleanup();
     p->state_ws = nullptr;
     return fail(QEW_EDEVICE, "run failed: %s", hipGetErrorString(he));
+  }
+  if (err_flags) {
+    cleanup();
+    p->state_ws = nullptr;
+    return fail(QEW_EUNSUPPORTED,
+                "the cells of a fused tile spread over 2^23 or more (state far from a line); "
+                "use the one-step path for this state");
   }
   for (int s = 0; s < p->S && n_meas > mi0; ++s) {
     for (int i = mi0; i < n_meas; ++i) {
