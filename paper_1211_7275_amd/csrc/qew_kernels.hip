@@ -191,7 +191,9 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 //      more cells), store the window, and write the new coefficients into the
 //      request slot;
 //   4. barrier; each requester reads its new coefficients.
-// A sub-step with no request at all skips 3-4.  After nsub <= halo
+// A sub-step with no request at all skips 3-4.  A wave posts at most
+// kReqPerWave requests per sub-step; the lanes of further requests (a burst
+// of simultaneous cell changes) regenerate their windows themselves.  After nsub <= halo
 // sub-steps the sites within `halo` of either tile end hold garbage (the tile
 // ends reflect), and the valid part [halo, halo + len) is written back with
 // its nodes.  Every value equals what the one-step kernel computes: the
@@ -205,7 +207,6 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 #define QEW_FUSED_MIN_WAVES 4
 #endif
 constexpr int kReqPerWave = QEW_REQ_PER_WAVE;
-constexpr float kCellSpan = 8388608.0f;  // 2^23
 
 template <int KIND, int P>
 __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
@@ -309,8 +310,14 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
       }
 
       // Euler step of every site (Jacobi: old values of the neighbours); a
-      // site that changed cell posts a request.
-      uint64_t moved[P];
+      // site that changed cell posts a request.  Byte i % 4 of rk[i / 4]
+      // holds k + 1 for the request of slot i (k: index in this wave's
+      // region), 0 if none; a site whose request does not fit the region is
+      // marked in `pending` and served by its own lane below.
+      uint32_t rk[(P + 3) / 4];
+#pragma unroll
+      for (int v = 0; v < (P + 3) / 4; ++v) rk[v] = 0u;
+      uint32_t pending = 0u;
       uint32_t nreq = 0u;  // wave-uniform
       float dl = c[0] - cle;  // cell difference to the left neighbour
       float pr = rle;
@@ -326,54 +333,31 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
         const float oc = c[i];
         const float fl = split_advance(r[i], F, dt);
         c[i] = oc + fl;
-        moved[i] = __ballot(fl != 0.0f);
+        const uint64_t moved = __ballot(fl != 0.0f);
         if (fl != 0.0f) {
-          const uint32_t k = nreq + mbcnt64(moved[i]);
-          if (k < (uint32_t)RQ)
+          const uint32_t k = nreq + mbcnt64(moved);
+          if (k < (uint32_t)RQ) {
             s_req[wv * RQ + k] = make_int4(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc), 0);
+            rk[i / 4] |= (k + 1u) << (8 * (i % 4));
+          } else {
+            pending |= 1u << i;
+          }
         }
-        nreq += (uint32_t)__popcll(moved[i]);
+        nreq += (uint32_t)__popcll(moved);
       }
       if (lane == 0) {
         s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
-        s_count[par][wv] = (int)nreq;
+        s_count[par][wv] = (int)(nreq < (uint32_t)RQ ? nreq : (uint32_t)RQ);
       }
       if (lane == 63) s_edge[par ^ 1][wv][1] = make_float2(c[P - 1], r[P - 1]);
       __syncthreads();
 
-      int cnt[NW];
-      int maxcnt = 0;
+      int pre[NW + 1];
+      pre[0] = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        cnt[w] = uniform_i32(s_count[par][w]);
-        maxcnt = cnt[w] > maxcnt ? cnt[w] : maxcnt;
-      }
-      const int rounds = (maxcnt + RQ - 1) / RQ;
-      for (int rd = 0; rd < rounds; ++rd) {
-        const uint32_t lo = (uint32_t)(rd * RQ);
-        if (rd > 0) {  // overflow: post the requests of this round
-          uint32_t n = 0u;
-#pragma unroll
-          for (int i = 0; i < P; ++i) {
-            if ((moved[i] >> lane) & 1u) {
-              const uint32_t k = n + mbcnt64(moved[i]);
-              if (k >= lo && k < lo + RQ)  // served by full regeneration of the window
-                s_req[wv * RQ + (k - lo)] =
-                    make_int4(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(c[i]), 0);
-            }
-            n += (uint32_t)__popcll(moved[i]);
-          }
-          __syncthreads();
-        }
-        // Serve the requests of this round with the whole workgroup.
-        int pre[NW + 1];
-        pre[0] = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          int cw = cnt[w] - rd * RQ;
-          cw = cw < 0 ? 0 : (cw > RQ ? RQ : cw);
-          pre[w + 1] = pre[w] + cw;
-        }
+      for (int w = 0; w < NW; ++w) pre[w + 1] = pre[w] + uniform_i32(s_count[par][w]);
+      if (pre[NW] > 0) {
+        // Serve the posted requests with the whole workgroup.
         for (int q = tid; q < pre[NW]; q += kBlock) {
           int w = 0;
 #pragma unroll
@@ -406,20 +390,34 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
         }
         __syncthreads();
         // Requesters read their new coefficients.
-        uint32_t n = 0u;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-          if ((moved[i] >> lane) & 1u) {
-            const uint32_t k = n + mbcnt64(moved[i]);
-            if (k >= lo && k < lo + RQ) {
-              const int4 v = s_req[wv * RQ + (k - lo)];
-              a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
-                                 __int_as_float(v.w));
-            }
+          const uint32_t k1 = (rk[i / 4] >> (8 * (i % 4))) & 0xffu;
+          if (k1 != 0u) {
+            const int4 v = s_req[wv * RQ + (int)k1 - 1];
+            a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
+                               __int_as_float(v.w));
           }
-          n += (uint32_t)__popcll(moved[i]);
         }
-        if (rd + 1 < rounds) __syncthreads();
+      }
+      // Rare: requests beyond the region (a burst of cell changes) are served
+      // by their own lane: regenerate the window of the new cell.
+      if (__ballot(pending != 0u)) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          if ((pending >> i) & 1u) {
+            int j = start_mod + tid * P + i;
+            if (j >= L) j -= L;
+            if (j >= L) j %= L;
+            const int32_t cell = cbase + (int32_t)c[i];
+            const float4 w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1),
+                                          node_f32<KIND>((uint32_t)j, cell, id, ph.k0, ph.k1),
+                                          node_f32<KIND>((uint32_t)j, cell + 1, id, ph.k0, ph.k1),
+                                          node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
+            s_nodes[i * kBlock + tid] = w4;
+            a[i] = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w, g, f);
+          }
+        }
       }
     }
 
