@@ -15,8 +15,10 @@ import numpy as np
 
 from . import build as _build
 
-RF = 0
-RB = 1
+RF = 0        # random field, uniform force values, Catmull-Rom
+RB = 1        # random bond, Gaussian potential, Catmull-Rom
+RB_LIN = 2    # random bond, Gaussian potential, linear spline (Case 3)
+RF_PC = 3     # random field, Gaussian forces, no interpolation (Case 4)
 
 _lib = None
 
@@ -36,25 +38,25 @@ def lib():
                                        ctypes.c_uint32, ctypes.c_double)
     L.qo_philox4x32_10.argtypes = [u32p, u32p, u32p]
     L.qo_philox_many.argtypes = [u32p, c_u64, u32p, c_i64]
-    L.qo_node.argtypes = [c_int, c_u64, c_u32, c_i64, c_i64]
+    L.qo_node.argtypes = [c_int, c_u64, c_u32, c_i64, c_i64, c_i64]
     L.qo_node.restype = c_d
     L.qo_cr_value.argtypes = [f64p, c_d]
     L.qo_cr_value.restype = c_d
     L.qo_cr_slope.argtypes = [f64p, c_d]
     L.qo_cr_slope.restype = c_d
-    L.qo_pinning.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d]
+    L.qo_pinning.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d, c_i64]
     L.qo_pinning.restype = c_d
-    L.qo_potential.argtypes = [c_d, c_u64, c_u32, c_i64, c_d]
+    L.qo_potential.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d, c_i64]
     L.qo_potential.restype = c_d
-    L.qo_forces.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d, c_d, f64p, f64p]
+    L.qo_forces.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_i64, c_d, c_d, f64p, f64p]
     L.qo_measure.argtypes = [c_i64, f64p, f64p, ctypes.POINTER(c_d), ctypes.POINTER(c_d),
                              ctypes.POINTER(c_d)]
     L.qo_euler.argtypes = [c_i64, c_d, f64p, f64p, f64p]
-    L.qo_run.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_d, c_d, c_d, c_i64, c_i64,
+    L.qo_run.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_i64, c_d, c_d, c_d, c_i64, c_i64,
                          i64p, ctypes.c_int32, f64p, f64p, f64p, f64p]
     L.qo_run.restype = c_int
-    L.qo_run_window.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_i64, c_i64, c_d, c_d, c_d,
-                                c_i64, f64p]
+    L.qo_run_window.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_i64, c_i64, c_i64, c_d, c_d,
+                                c_d, c_i64, f64p]
     L.qo_run_window.restype = c_int
     L.qo_mean_node.argtypes = [c_int, c_u64, c_u32, c_i64, c_i64]
     L.qo_mean_node.restype = c_d
@@ -87,9 +89,9 @@ def philox_many(ctr, seed):
     return out
 
 
-def node(kind, seed, did, j, n):
+def node(kind, seed, did, j, n, period=0):
     """Unscaled disorder value at integer u = n of column j."""
-    return lib().qo_node(int(kind), int(seed), int(did), int(j), int(n))
+    return lib().qo_node(int(kind), int(seed), int(did), int(j), int(n), int(period))
 
 
 def cr_value(p, s):
@@ -100,19 +102,21 @@ def cr_slope(p, s):
     return lib().qo_cr_slope(np.ascontiguousarray(p, np.float64), float(s))
 
 
-def pinning(kind, strength, seed, did, j, u):
-    return lib().qo_pinning(int(kind), float(strength), int(seed), int(did), int(j), float(u))
+def pinning(kind, strength, seed, did, j, u, period=0):
+    return lib().qo_pinning(int(kind), float(strength), int(seed), int(did), int(j), float(u),
+                            int(period))
 
 
-def potential(strength, seed, did, j, u):
-    return lib().qo_potential(float(strength), int(seed), int(did), int(j), float(u))
+def potential(strength, seed, did, j, u, kind=RB, period=0):
+    return lib().qo_potential(int(kind), float(strength), int(seed), int(did), int(j), float(u),
+                              int(period))
 
 
-def forces(kind, strength, seed, did, c, f, u):
+def forces(kind, strength, seed, did, c, f, u, period=0):
     u = np.ascontiguousarray(u, np.float64)
     F = np.zeros_like(u)
-    lib().qo_forces(int(kind), float(strength), int(seed), int(did), u.size, float(c),
-                    float(f), u, F)
+    lib().qo_forces(int(kind), float(strength), int(seed), int(did), int(period), u.size,
+                    float(c), float(f), u, F)
     return F
 
 
@@ -133,32 +137,33 @@ def euler(dt, u, F):
 
 
 def run_sample(kind, strength, seed, did, L, c, dt, f, n_steps, meas_steps,
-               u0=None, step0=0):
+               u0=None, step0=0, period=0):
     """Evolve one sample; returns dict(v, ubar, w2, u) (u = state at n_steps)."""
     meas = np.ascontiguousarray(meas_steps, np.int64)
     u = np.zeros(int(L), np.float64) if u0 is None else np.array(u0, np.float64, copy=True)
     v = np.full(meas.size, np.nan)
     ub = np.full(meas.size, np.nan)
     w2 = np.full(meas.size, np.nan)
-    rc = lib().qo_run(int(kind), float(strength), int(seed), int(did), int(L), float(c),
-                      float(dt), float(f), int(step0), int(n_steps), meas,
+    rc = lib().qo_run(int(kind), float(strength), int(seed), int(did), int(period), int(L),
+                      float(c), float(dt), float(f), int(step0), int(n_steps), meas,
                       int(meas.size), u, v, ub, w2)
     if rc != 0:
         raise ValueError("oracle qo_run rejected its input")
     return {"v": v, "ubar": ub, "w2": w2, "u": u}
 
 
-def site_after(kind, strength, seed, did, L, j, c, dt, f, n_steps):
+def site_after(kind, strength, seed, did, L, j, c, dt, f, n_steps, period=0):
     """u_j after n_steps from the flat start on the periodic chain of length L,
     computed on the light-cone window of sites j - n_steps - 1 .. j + n_steps + 1."""
     half = int(n_steps) + 1
     W = 2 * half + 1
     if W >= L:
-        r = run_sample(kind, strength, seed, did, L, c, dt, f, n_steps, [])
+        r = run_sample(kind, strength, seed, did, L, c, dt, f, n_steps, [], period=period)
         return r["u"][int(j)]
     u = np.zeros(W, np.float64)
-    rc = lib().qo_run_window(int(kind), float(strength), int(seed), int(did), int(L),
-                             int(j) - half, W, float(c), float(dt), float(f), int(n_steps), u)
+    rc = lib().qo_run_window(int(kind), float(strength), int(seed), int(did), int(period),
+                             int(L), int(j) - half, W, float(c), float(dt), float(f),
+                             int(n_steps), u)
     if rc != 0:
         raise ValueError("oracle qo_run_window rejected its input")
     return u[half]
@@ -182,7 +187,7 @@ def run(problem, u0=None, step0=0):
         r = run_sample(problem["kind"], problem["strength"], problem["seed"],
                        problem["disorder_id"][s], problem["L"][s], problem["c"],
                        problem["dt"], problem["f"][s], problem["n_steps"], meas,
-                       None if u0 is None else u0[s], step0)
+                       None if u0 is None else u0[s], step0, problem.get("period", 0))
         for k in ("v", "ubar", "w2"):
             out[k][s] = r[k]
         states.append(r["u"])

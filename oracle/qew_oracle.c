@@ -32,7 +32,14 @@
  *   - spline: uniform Catmull-Rom (cardinal, tension 1/2) over the nodes
  *     n-1 .. n+2, which is local, C^1 and exact at the nodes;
  *   - node values are multiplied by `strength`;
- *   - the Euler update is synchronous (every site reads step-m values).
+ *   - the Euler update is synchronous (every site reads step-m values);
+ *   - Sec. IV C, Case 3 (RB, Gaussian potential, linear spline): between
+ *     integers the potential is linear, so F_p = -(V(n+1) - V(n)) on
+ *     [n, n+1), discontinuous at the integers;
+ *   - Sec. IV C, Case 4 (RF, Gaussian forces, no interpolation): F_p = R(n)
+ *     on [n, n+1) (the value of the integer below u);
+ *   - optional transverse period M (Sec. III B: the u direction can be made
+ *     periodic): node n is node n mod M (M = 0: no period).
  *
  * Precision and order: everything is IEEE binary64, round to nearest, and the
  * file must be built with -ffp-contract=off so that no multiply-add is fused.
@@ -51,8 +58,10 @@
 #include <omp.h>
 #endif
 
-#define QO_RF 0
-#define QO_RB 1
+#define QO_RF 0      /* random field, uniform force values, Catmull-Rom  */
+#define QO_RB 1      /* random bond, Gaussian potential, Catmull-Rom     */
+#define QO_RB_LIN 2  /* random bond, Gaussian potential, linear spline   */
+#define QO_RF_PC 3   /* random field, Gaussian forces, no interpolation  */
 
 /* ------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the Philox S-box */
@@ -90,9 +99,10 @@ void qo_philox_many(const uint32_t *ctr, uint64_t seed, uint32_t *out, int64_t n
 /* ------------------------------------------------------------------ */
 /* Disorder node value R(j, n) at integer u = n of column j (unscaled). */
 /* ------------------------------------------------------------------ */
-double qo_node(int kind, uint64_t seed, uint32_t disorder_id, int64_t j, int64_t n)
+double qo_node(int kind, uint64_t seed, uint32_t disorder_id, int64_t j, int64_t n, int64_t period)
 {
     uint32_t ctr[4], key[2], x[4];
+    if (period > 0) n = ((n % period) + period) % period;
     ctr[0] = (uint32_t)j;
     ctr[1] = (uint32_t)(int32_t)n;          /* two's complement of the signed cell */
     ctr[2] = disorder_id;
@@ -142,28 +152,42 @@ double qo_cr_slope(const double p[4], double s)
 /* Pinning force F_p(u, j) (Sec. III B; RB: F_p = -dU/du, Sec. II).     */
 /* ------------------------------------------------------------------ */
 double qo_pinning(int kind, double strength, uint64_t seed, uint32_t disorder_id,
-                  int64_t j, double u)
+                  int64_t j, double u, int64_t period)
 {
     if (strength == 0.0) return 0.0;
     double nf = floor(u);
     int64_t n = (int64_t)nf;
     double s = u - nf;                       /* exact for |u| < 2^52 */
+    if (kind == QO_RB_LIN) {                 /* F_p = -(V(n+1) - V(n)) */
+        double v0 = strength * qo_node(kind, seed, disorder_id, j, n, period);
+        double v1 = strength * qo_node(kind, seed, disorder_id, j, n + 1, period);
+        return -(v1 - v0);
+    }
+    if (kind == QO_RF_PC)                    /* F_p = R(n) */
+        return strength * qo_node(kind, seed, disorder_id, j, n, period);
     double p[4];
     for (int i = 0; i < 4; ++i)
-        p[i] = strength * qo_node(kind, seed, disorder_id, j, n - 1 + i);
+        p[i] = strength * qo_node(kind, seed, disorder_id, j, n - 1 + i, period);
     if (kind == QO_RF)
         return qo_cr_value(p, s);
     return -qo_cr_slope(p, s);
 }
 
-/* Interpolated potential U(u, j) for RB (used by the tests only). */
-double qo_potential(double strength, uint64_t seed, uint32_t disorder_id, int64_t j, double u)
+/* Interpolated potential U(u, j) of the random-bond kinds (tests only):
+ * Catmull-Rom (QO_RB) or linear (QO_RB_LIN) in u. */
+double qo_potential(int kind, double strength, uint64_t seed, uint32_t disorder_id, int64_t j,
+                    double u, int64_t period)
 {
     double nf = floor(u);
     int64_t n = (int64_t)nf;
+    if (kind == QO_RB_LIN) {
+        double v0 = strength * qo_node(kind, seed, disorder_id, j, n, period);
+        double v1 = strength * qo_node(kind, seed, disorder_id, j, n + 1, period);
+        return v0 + (v1 - v0) * (u - nf);
+    }
     double p[4];
     for (int i = 0; i < 4; ++i)
-        p[i] = strength * qo_node(QO_RB, seed, disorder_id, j, n - 1 + i);
+        p[i] = strength * qo_node(QO_RB, seed, disorder_id, j, n - 1 + i, period);
     return qo_cr_value(p, u - nf);
 }
 
@@ -171,7 +195,7 @@ double qo_potential(double strength, uint64_t seed, uint32_t disorder_id, int64_
 /* Total force on every site at one time (Eq. (1), periodic in x):      */
 /*   F_j = ((c * ((u_{j+1} + u_{j-1}) - 2 u_j)) + f) + F_p(u_j, j)      */
 /* ------------------------------------------------------------------ */
-void qo_forces(int kind, double strength, uint64_t seed, uint32_t disorder_id,
+void qo_forces(int kind, double strength, uint64_t seed, uint32_t disorder_id, int64_t period,
                int64_t L, double c, double f, const double *u, double *F)
 {
     int64_t j;
@@ -182,7 +206,7 @@ void qo_forces(int kind, double strength, uint64_t seed, uint32_t disorder_id,
         int64_t jm = (j == 0) ? L - 1 : j - 1;
         int64_t jp = (j == L - 1) ? 0 : j + 1;
         double lap = (u[jp] + u[jm]) - 2.0 * u[j];
-        double fp = qo_pinning(kind, strength, seed, disorder_id, j, u[j]);
+        double fp = qo_pinning(kind, strength, seed, disorder_id, j, u[j], period);
         F[j] = ((c * lap) + f) + fp;
     }
 }
@@ -230,7 +254,7 @@ void qo_euler(int64_t L, double dt, const double *u, const double *F, double *u_
  * to v/ubar/w2[index of m]; entries for m < step0 are left untouched.  On
  * return `u` holds the state at step n_steps.  Returns 0, or -1 on bad input.
  */
-int qo_run(int kind, double strength, uint64_t seed, uint32_t disorder_id,
+int qo_run(int kind, double strength, uint64_t seed, uint32_t disorder_id, int64_t period,
            int64_t L, double c, double dt, double f,
            int64_t step0, int64_t n_steps, const int64_t *meas_steps, int32_t n_meas,
            double *u, double *v, double *ubar, double *w2)
@@ -244,7 +268,7 @@ int qo_run(int kind, double strength, uint64_t seed, uint32_t disorder_id,
     for (int64_t m = step0; m <= n_steps; ++m) {
         int measure = (mi < n_meas && meas_steps[mi] == m);
         if (!measure && m == n_steps) break;
-        qo_forces(kind, strength, seed, disorder_id, L, c, f, u, F);
+        qo_forces(kind, strength, seed, disorder_id, period, L, c, f, u, F);
         if (measure) {
             qo_measure(L, u, F, &v[mi], &ubar[mi], &w2[mi]);
             ++mi;
@@ -269,7 +293,7 @@ int qo_run(int kind, double strength, uint64_t seed, uint32_t disorder_id,
  * periodic chain of length L_global.  `u` holds the window's state on entry
  * and on return.  Returns 0, or -1 on bad input.
  */
-int qo_run_window(int kind, double strength, uint64_t seed, uint32_t disorder_id,
+int qo_run_window(int kind, double strength, uint64_t seed, uint32_t disorder_id, int64_t period,
                   int64_t L_global, int64_t j0, int64_t W, double c, double dt, double f,
                   int64_t n_steps, double *u)
 {
@@ -287,7 +311,7 @@ int qo_run_window(int kind, double strength, uint64_t seed, uint32_t disorder_id
             int64_t ip = (i == W - 1) ? 0 : i + 1;
             int64_t j = ((j0 + i) % L_global + L_global) % L_global;
             double lap = (u[ip] + u[im]) - 2.0 * u[i];
-            double fp = qo_pinning(kind, strength, seed, disorder_id, j, u[i]);
+            double fp = qo_pinning(kind, strength, seed, disorder_id, j, u[i], period);
             F[i] = ((c * lap) + f) + fp;
         }
         qo_euler(W, dt, u, F, un);
@@ -303,7 +327,7 @@ double qo_mean_node(int kind, uint64_t seed, uint32_t disorder_id, int64_t L, in
 {
     double s = 0.0, comp = 0.0;
     for (int64_t j = 0; j < L; ++j) {
-        double x = qo_node(kind, seed, disorder_id, j, n);
+        double x = qo_node(kind, seed, disorder_id, j, n, 0);
         double t = s + x;
         if (fabs(s) >= fabs(x)) comp += (s - t) + x;
         else comp += (x - t) + s;

@@ -229,7 +229,7 @@ def test_periodic_bump_spreads_symmetrically(oracle):
 
 # ------------------------------------------------ invariants with disorder --
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_mean_velocity_identity(oracle, kind):
     """d<u>/dt = f + <F_p> (the Laplacian sums to zero under periodic boundaries),
     and v is the mean total force (Eq. (3)): ubar(m+1) - ubar(m) = dt v(m)."""
@@ -305,7 +305,7 @@ def _slope_dec(p, s):
     return (c1 + s * (2 * c2 + s * 3 * c3)) / 2
 
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_fp64_rounding_against_60_digit_evaluation(oracle, kind):
     """The FP64 trajectory agrees with a 60-digit decimal evaluation of the same
     map (same node values) to 1e-12 after 200 steps at L = 8."""
@@ -328,7 +328,14 @@ def test_fp64_rounding_against_60_digit_evaluation(oracle, kind):
             n = int(u[j].to_integral_value(rounding=decimal.ROUND_FLOOR))
             s = u[j] - n
             p = [node(j, n - 1 + i) for i in range(4)]
-            fp = _cr_dec(p, s) if kind == 0 else -_slope_dec(p, s)
+            if kind == 0:
+                fp = _cr_dec(p, s)
+            elif kind == 1:
+                fp = -_slope_dec(p, s)
+            elif kind == 2:
+                fp = -(p[2] - p[1])
+            else:
+                fp = p[1]
             lap = u[(j + 1) % L] + u[(j - 1) % L] - 2 * u[j]
             new.append(u[j] + Ddt * (Dc * lap + Df + fp))
         u = new
@@ -353,3 +360,61 @@ def test_mean_node_at_zero_is_initial_mean_force(oracle):
     L = 500
     r = oracle.run_sample(0, 0.8, SEED, 2, L, 1.0, 0.05, 1.1, 0, [0])
     assert abs(r["v"][0] - (1.1 + 0.8 * oracle.mean_node(0, SEED, 2, L, 0))) < 1e-14
+
+
+# ------------------------------------- Cases 3 and 4, transverse period ----
+
+def test_linear_spline_rb_force(oracle):
+    """Case 3 (Sec. IV C): Gaussian potential, linear spline.  The potential is
+    continuous at the integers, the force is constant inside a cell and equals
+    -dU/du there, and the forces telescope: sum over cells a..b-1 of F is
+    -(U(b) - U(a))."""
+    RBL = oracle.RB_LIN
+    rng = np.random.default_rng(21)
+    for _ in range(100):
+        j = int(rng.integers(0, 5000))
+        n = int(rng.integers(-50, 50))
+        s1, s2 = rng.uniform(0.01, 0.99, size=2)
+        f1 = oracle.pinning(RBL, 1.3, SEED, 2, j, n + s1)
+        assert f1 == oracle.pinning(RBL, 1.3, SEED, 2, j, n + s2)
+        h = 1e-6
+        fd = (oracle.potential(1.3, SEED, 2, j, n + s1 + h, kind=RBL)
+              - oracle.potential(1.3, SEED, 2, j, n + s1 - h, kind=RBL)) / (2 * h)
+        assert abs(f1 + fd) < 1e-7
+        assert abs(oracle.potential(1.3, SEED, 2, j, n - 1e-13, kind=RBL)
+                   - oracle.potential(1.3, SEED, 2, j, float(n), kind=RBL)) < 1e-11
+    j, a, b = 77, -20, 35
+    tot = sum(oracle.pinning(RBL, 0.9, SEED, 1, j, m + 0.5) for m in range(a, b))
+    Ua = oracle.potential(0.9, SEED, 1, j, float(a), kind=RBL)
+    Ub = oracle.potential(0.9, SEED, 1, j, float(b), kind=RBL)
+    assert abs(tot + (Ub - Ua)) < 1e-12
+    # the potential values at the integers are the N(0, 1) nodes times strength
+    assert Ua == 0.9 * oracle.node(RBL, SEED, 1, j, a)
+
+
+def test_piecewise_constant_rf_force(oracle):
+    """Case 4: Gaussian random forces without interpolation: F_p = strength R(n)
+    on [n, n+1), with R standard normal; it jumps at the integers."""
+    RFP = oracle.RF_PC
+    vals = []
+    for j in range(60):
+        for n in range(-30, 30):
+            f = oracle.pinning(RFP, 0.5, SEED, 3, j, n + 0.25)
+            assert f == oracle.pinning(RFP, 0.5, SEED, 3, j, n + 0.999)
+            assert f == oracle.pinning(RFP, 0.5, SEED, 3, j, float(n))
+            vals.append(f / 0.5)
+    vals = np.array(vals)
+    assert stats.kstest(vals, stats.norm.cdf).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_transverse_period(oracle, kind):
+    """Optional period M in u (Sec. III B): node n is node n mod M, so the
+    pinning force is periodic with period M; M = 0 keeps the infinite medium."""
+    M = 7
+    for j in (0, 9, 1234):
+        for n in (-15, -1, 0, 3, 6, 7, 30):
+            assert oracle.node(kind, SEED, 4, j, n, M) == oracle.node(kind, SEED, 4, j, n % M)
+        for u in (-3.25, 0.0, 0.5, 2.75, 6.9921875):  # dyadic, so u + M is exact
+            assert oracle.pinning(kind, 1.0, SEED, 4, j, u, M) == oracle.pinning(kind, 1.0, SEED, 4, j, u + M, M)
+    assert oracle.node(kind, SEED, 4, 5, 9) != oracle.node(kind, SEED, 4, 5, 2)
