@@ -15,6 +15,9 @@
  *     interpolated in u by a cubic (Catmull-Rom) spline (Sec. III B).  Random
  *     field: the values are forces, uniform in (-1, 1).  Random bond: the
  *     values are potential energies, N(0, 1), and F_p = -dU/du (Sec. II).
+ *     Also the paper's Case 3 (Gaussian potential, linear spline) and Case 4
+ *     (Gaussian forces, no interpolation) of Sec. IV C, and an optional
+ *     transverse period M of the medium in u (Sec. III B).
  *     Values are scaled by `strength`.  Generator: Philox4x32-10 (Salmon et
  *     al., SC'11) with counter (j, (uint32) n, disorder_id, 0) and key
  *     (seed low word, seed high word).
@@ -53,9 +56,11 @@ typedef int32_t qew_status;
 #define QEW_EDEVICE      (-3) /* HIP error; workspace contents undefined, plan valid */
 #define QEW_EUNSUPPORTED (-4) /* valid but not implemented combination             */
 
-/* disorder kinds (Sec. III B; RF = random field, RB = random bond) */
+/* disorder kinds (Sec. III B; RF = random field, RB = random bond; Sec. IV C cases) */
 #define QEW_RF_CR_UNIFORM 0   /* force values uniform in (-1,1), Catmull-Rom in u     */
 #define QEW_RB_CR_GAUSS   1   /* potential values N(0,1), Catmull-Rom, F_p = -dU/du   */
+#define QEW_RB_LIN_GAUSS  2   /* Case 3: potential N(0,1), linear in u: F_p = -(V(n+1) - V(n)) */
+#define QEW_RF_PC_GAUSS   3   /* Case 4: force values N(0,1), no interpolation: F_p = R(n)    */
 
 /* arithmetic of the integrator */
 #define QEW_FP64_PLAIN 0      /* u in FP64                                             */
@@ -94,6 +99,8 @@ typedef struct qew_problem {
   int32_t         k;            /* fused: steps per launch, 1..64 (0 = autotune)        */
   int32_t         tile;         /* fused: sites per wave tile, 512/1024/2048 (0 = autotune); 4k <= tile */
   int32_t         flags;        /* QEW_FLAG_* bits                                      */
+  int32_t         period;       /* transverse period M of the disorder in u (node n is
+                                   node n mod M); 0 = no period; else 1 <= M < 2^30     */
 } qew_problem;
 
 typedef struct qew_plan_s qew_plan_t;
@@ -200,15 +207,17 @@ qew_status qew_debug_philox_fill(const uint32_t *d_ctr, uint64_t seed, uint32_t 
                                  int64_t N, void *stream);
 
 /*
- * Debug: pinning force F_p at N points, in the arithmetic of `precision`.
+ * Debug: pinning force F_p at N points (disorder `kind`, transverse period
+ * `period`, 0 = none), in the arithmetic of `precision`.
  * Point i: column d_j[i], disorder id d_did[i], u = d_cell[i] + d_frac[i]
  * (FP64 path: u formed in FP64 then floored; split path: cell as given and
  * offset rounded to FP32, which must lie in [0, 1)).  d_out: device [N] FP64.
  * Asynchronous on `stream`.
  */
-qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, int32_t precision,
-                                const uint32_t *d_did, const int32_t *d_j, const int32_t *d_cell,
-                                const double *d_frac, double *d_out, int64_t N, void *stream);
+qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, int32_t period,
+                                int32_t precision, const uint32_t *d_did, const int32_t *d_j,
+                                const int32_t *d_cell, const double *d_frac, double *d_out,
+                                int64_t N, void *stream);
 
 /* Free a plan (NULL is allowed); releases its hipGraphs. */
 void qew_plan_destroy(qew_plan_t *plan);

@@ -22,8 +22,10 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kWeyl0 = 0x9E3779B9u;
 constexpr uint32_t kWeyl1 = 0xBB67AE85u;
 
-constexpr int kRF = 0;
-constexpr int kRB = 1;
+constexpr int kRF = 0;     // random field, uniform force values, Catmull-Rom
+constexpr int kRB = 1;     // random bond, Gaussian potential, Catmull-Rom
+constexpr int kRBLin = 2;  // random bond, Gaussian potential, linear spline (Case 3)
+constexpr int kRFPc = 3;   // random field, Gaussian forces, no interpolation (Case 4)
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
 // products with the Weyl-bumped key.  The 64-bit product maps to one
@@ -45,10 +47,17 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
   }
 }
 
-// Raw words of the disorder generator at (j, n): counter (j, (uint32)n, id, 0).
+// Raw words of the disorder generator at (j, n): counter (j, (uint32)n, id, 0),
+// with n taken modulo the transverse period when there is one.
 struct NodeWords {
   uint32_t x0, x1;
 };
+
+__device__ __forceinline__ int32_t wrap_cell(int32_t n, int32_t period) {
+  if (period <= 0) return n;
+  int32_t m = n % period;
+  return m < 0 ? m + period : m;
+}
 
 __device__ __forceinline__ NodeWords node_words(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
                                                 uint32_t k1) {
@@ -83,10 +92,12 @@ __device__ __forceinline__ double rb_value_f64(uint32_t x0, uint32_t x1) {
   return radius * cos(angle);
 }
 
+// Node value at (j, n): uniform for kRF, N(0, 1) (Box-Muller) for the other
+// kinds; n is wrapped by the transverse period `period` (0: none).
 template <int KIND>
 __device__ __forceinline__ float node_f32(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
-                                          uint32_t k1) {
-  const NodeWords w = node_words(j, n, id, k0, k1);
+                                          uint32_t k1, int32_t period) {
+  const NodeWords w = node_words(j, wrap_cell(n, period), id, k0, k1);
   if constexpr (KIND == kRF) {
     return (float)rf_odd(w.x0) * 0x1p-24f;
   } else {
@@ -96,8 +107,8 @@ __device__ __forceinline__ float node_f32(uint32_t j, int32_t n, uint32_t id, ui
 
 template <int KIND>
 __device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
-                                           uint32_t k1) {
-  const NodeWords w = node_words(j, n, id, k0, k1);
+                                           uint32_t k1, int32_t period) {
+  const NodeWords w = node_words(j, wrap_cell(n, period), id, k0, k1);
   if constexpr (KIND == kRF) {
     return (double)rf_odd(w.x0) * 0x1p-24;
   } else {
@@ -121,9 +132,16 @@ __device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, u
 // every kernel goes through these two functions, so a cached coefficient set
 // gives exactly the force a fresh evaluation gives.
 // ---------------------------------------------------------------------------
+//   Case 3 (kRBLin): {f + g (p2 - p1), 0, 0, 0} with g = -strength, constant in the cell;
+//   Case 4 (kRFPc):  {f + g p1, 0, 0, 0} with g = +strength.
 template <int KIND>
 __device__ __forceinline__ float4 spline_coef(float p0, float p1, float p2, float p3, float g,
                                               float f) {
+  if constexpr (KIND == kRBLin) {
+    return make_float4(fmaf(g, p2 - p1, f), 0.0f, 0.0f, 0.0f);
+  } else if constexpr (KIND == kRFPc) {
+    return make_float4(fmaf(g, p1, f), 0.0f, 0.0f, 0.0f);
+  }
   const float a1 = 0.5f * (p2 - p0);
   const float d30 = p3 - p0;
   const float d12 = p1 - p2;
@@ -142,15 +160,30 @@ template <int KIND>
 __device__ __forceinline__ float spline_eval(const float4& a, float s) {
   if constexpr (KIND == kRF) {
     return fmaf(s, fmaf(s, fmaf(s, a.w, a.z), a.y), a.x);
-  } else {
+  } else if constexpr (KIND == kRB) {
     return fmaf(s, fmaf(s, a.z, a.y), a.x);
+  } else {
+    return a.x;  // piecewise constant in the cell
   }
 }
 
+// Sign of the node-value scale: +strength for force values, -strength for
+// potential values (F_p = -dU/du).
+template <int KIND>
+__device__ __forceinline__ float kind_sign() {
+  return (KIND == kRF || KIND == kRFPc) ? 1.0f : -1.0f;
+}
+
 // FP64 form, same operation order as the textbook polynomial
-// 1/2 [2 p1 + (p2 - p0) s + (2p0 - 5p1 + 4p2 - p3) s^2 + (-p0 + 3p1 - 3p2 + p3) s^3].
+// 1/2 [2 p1 + (p2 - p0) s + (2p0 - 5p1 + 4p2 - p3) s^2 + (-p0 + 3p1 - 3p2 + p3) s^3];
+// Case 3: -(p2 - p1); Case 4: p1 (p scaled by strength).
 template <int KIND>
 __device__ __forceinline__ double spline_f64(const double p[4], double s) {
+  if constexpr (KIND == kRBLin) {
+    return -(p[2] - p[1]);
+  } else if constexpr (KIND == kRFPc) {
+    return p[1];
+  }
   const double c1 = p[2] - p[0];
   const double c2 = 2.0 * p[0] - 5.0 * p[1] + 4.0 * p[2] - p[3];
   const double c3 = -p[0] + 3.0 * p[1] - 3.0 * p[2] + p[3];
@@ -203,16 +236,19 @@ struct PlainPhys {
 template <int KIND>
 __device__ __forceinline__ double plain_force(double ul, double u, double ur, uint32_t j,
                                               uint32_t id, uint32_t k0, uint32_t k1, double f,
-                                              const PlainPhys& ph) {
+                                              int32_t period, const PlainPhys& ph) {
   const double lap = (ur + ul) - 2.0 * u;
   double fp = 0.0;
   if (ph.strength != 0.0) {
     const double nf = floor(u);
     const int32_t n = (int32_t)nf;
     const double s = u - nf;
-    double p[4];
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    // Catmull-Rom needs nodes n-1..n+2, Case 3 n..n+1, Case 4 n.
+    constexpr int lo = (KIND == kRF || KIND == kRB) ? 0 : 1;
+    constexpr int hi = (KIND == kRF || KIND == kRB) ? 4 : (KIND == kRBLin ? 3 : 2);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) p[i] = ph.strength * node_f64<KIND>(j, n - 1 + i, id, k0, k1);
+    for (int i = lo; i < hi; ++i) p[i] = ph.strength * node_f64<KIND>(j, n - 1 + i, id, k0, k1, period);
     fp = spline_f64<KIND>(p, s);
   }
   return ((ph.c * lap) + f) + fp;

@@ -33,8 +33,9 @@ struct SplitBuf {
 
 struct Phys {
   double c, dt, strength;
-  float cf, dtf, sgn_strf;  // FP32 copies; sgn_strf = +strength (RF) or -strength (RB)
+  float cf, dtf, sgn_strf;  // FP32 copies; sgn_strf = +strength (force values) or -strength (potential)
   uint32_t k0, k1;          // Philox key (seed words)
+  int32_t period;           // transverse period of the disorder in u (0: none)
 };
 
 // Measurement partial of one tile: sum of F, sum of (u - K), sum of (u - K)^2, K.
@@ -72,7 +73,8 @@ hipError_t launch_fill_f64(double* p, int64_t n, double value, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t n, int value, hipStream_t st);
 hipError_t launch_philox_fill(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                               int64_t n, hipStream_t st);
-hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int precision,
+hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int32_t period,
+                             int precision,
                              const uint32_t* did, const int32_t* j, const int32_t* cell,
                              const double* frac, double* out, int64_t n, hipStream_t st);
 

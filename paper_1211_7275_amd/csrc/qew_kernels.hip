@@ -98,10 +98,10 @@ __global__ void __launch_bounds__(kBlock)
     }
     if (with_nodes) {
       float4 nd;
-      nd.x = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1);
-      nd.y = node_f32<KIND>(j, c, id, ph.k0, ph.k1);
-      nd.z = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1);
-      nd.w = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1);
+      nd.x = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1, ph.period);
+      nd.y = node_f32<KIND>(j, c, id, ph.k0, ph.k1, ph.period);
+      nd.z = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1, ph.period);
+      nd.w = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period);
       b.nodes[base + j] = nd;
     }
   }
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kBlock)
     const int jp = (j == L - 1) ? 0 : j + 1;
     const double u = uin[base + j];
     const double F = plain_force<KIND>(uin[base + jm], u, uin[base + jp], (uint32_t)j, id, ph.k0,
-                                       ph.k1, f, pp);
+                                       ph.k1, f, ph.period, pp);
     uout[base + j] = u + ph.dt * F;
   }
 }
@@ -139,10 +139,12 @@ __device__ __forceinline__ void nodes_of(uint32_t j, int32_t c, uint32_t id, con
     p0 = p1 = p2 = p3 = 0.0f;
     return;
   }
-  p0 = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1);
-  p1 = node_f32<KIND>(j, c, id, ph.k0, ph.k1);
-  p2 = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1);
-  p3 = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1);
+  // Catmull-Rom needs nodes c-1..c+2, Case 3 c..c+1, Case 4 c only.
+  constexpr bool cubic = (KIND == kRF || KIND == kRB);
+  p0 = cubic ? node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1, ph.period) : 0.0f;
+  p1 = node_f32<KIND>(j, c, id, ph.k0, ph.k1, ph.period);
+  p2 = (KIND != kRFPc) ? node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1, ph.period) : 0.0f;
+  p3 = cubic ? node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period) : 0.0f;
 }
 
 template <int KIND>
@@ -374,14 +376,14 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
           if (j >= L) j %= L;
           float4 w4 = s_nodes[ni];
           if (move == 1.0f) {
-            w4 = make_float4(w4.y, w4.z, w4.w, node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
+            w4 = make_float4(w4.y, w4.z, w4.w, node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1, ph.period));
           } else if (move == -1.0f) {
-            w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1), w4.x, w4.y, w4.z);
+            w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1, ph.period), w4.x, w4.y, w4.z);
           } else {
-            w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1),
-                             node_f32<KIND>((uint32_t)j, cell, id, ph.k0, ph.k1),
-                             node_f32<KIND>((uint32_t)j, cell + 1, id, ph.k0, ph.k1),
-                             node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
+            w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1, ph.period),
+                             node_f32<KIND>((uint32_t)j, cell, id, ph.k0, ph.k1, ph.period),
+                             node_f32<KIND>((uint32_t)j, cell + 1, id, ph.k0, ph.k1, ph.period),
+                             node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1, ph.period));
           }
           s_nodes[ni] = w4;
           const float4 co = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w, g, f);
@@ -410,10 +412,10 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
             if (j >= L) j -= L;
             if (j >= L) j %= L;
             const int32_t cell = cbase + (int32_t)c[i];
-            const float4 w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1),
-                                          node_f32<KIND>((uint32_t)j, cell, id, ph.k0, ph.k1),
-                                          node_f32<KIND>((uint32_t)j, cell + 1, id, ph.k0, ph.k1),
-                                          node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1));
+            const float4 w4 = make_float4(node_f32<KIND>((uint32_t)j, cell - 1, id, ph.k0, ph.k1, ph.period),
+                                          node_f32<KIND>((uint32_t)j, cell, id, ph.k0, ph.k1, ph.period),
+                                          node_f32<KIND>((uint32_t)j, cell + 1, id, ph.k0, ph.k1, ph.period),
+                                          node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1, ph.period));
             s_nodes[i * kBlock + tid] = w4;
             a[i] = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w, g, f);
           }
@@ -474,7 +476,8 @@ __global__ void __launch_bounds__(kBlock)
     const int jm = (j == 0) ? L - 1 : j - 1;
     const int jp = (j == L - 1) ? 0 : j + 1;
     const double uj = u[base + j];
-    sf += plain_force<KIND>(u[base + jm], uj, u[base + jp], (uint32_t)j, id, ph.k0, ph.k1, f, pp);
+    sf += plain_force<KIND>(u[base + jm], uj, u[base + jp], (uint32_t)j, id, ph.k0, ph.k1, f, ph.period,
+                            pp);
     const double x = uj - K;
     s1 += x;
     s2 += x * x;
@@ -633,7 +636,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <int KIND>
 __global__ void __launch_bounds__(kBlock)
-    k_force_eval(double strength, uint32_t k0, uint32_t k1, int precision,
+    k_force_eval(double strength, uint32_t k0, uint32_t k1, int32_t period, int precision,
                  const uint32_t* __restrict__ did, const int32_t* __restrict__ jj,
                  const int32_t* __restrict__ cell, const double* __restrict__ frac,
                  double* __restrict__ out, int64_t n) {
@@ -647,16 +650,16 @@ __global__ void __launch_bounds__(kBlock)
     const int32_t c = (int32_t)nf;
     double p[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) p[q] = strength * node_f64<KIND>(j, c - 1 + q, id, k0, k1);
+    for (int q = 0; q < 4; ++q) p[q] = strength * node_f64<KIND>(j, c - 1 + q, id, k0, k1, period);
     out[i] = spline_f64<KIND>(p, u - nf);
   } else {
     const int32_t c = cell[i];
     const float r = (float)frac[i];
-    const float p0 = node_f32<KIND>(j, c - 1, id, k0, k1);
-    const float p1 = node_f32<KIND>(j, c, id, k0, k1);
-    const float p2 = node_f32<KIND>(j, c + 1, id, k0, k1);
-    const float p3 = node_f32<KIND>(j, c + 2, id, k0, k1);
-    const float sg = (KIND == kRF) ? (float)strength : -(float)strength;
+    const float p0 = node_f32<KIND>(j, c - 1, id, k0, k1, period);
+    const float p1 = node_f32<KIND>(j, c, id, k0, k1, period);
+    const float p2 = node_f32<KIND>(j, c + 1, id, k0, k1, period);
+    const float p3 = node_f32<KIND>(j, c + 2, id, k0, k1, period);
+    const float sg = kind_sign<KIND>() * (float)strength;
     out[i] = (double)spline_eval<KIND>(spline_coef<KIND>(p0, p1, p2, p3, sg, 0.0f), r);
   }
 }
@@ -666,10 +669,12 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 #define QEW_KIND_DISPATCH(kind, KERNEL, ...)                      \
   do {                                                            \
-    if ((kind) == kRF)                                            \
-      hipLaunchKernelGGL(KERNEL<kRF>, __VA_ARGS__);               \
-    else                                                          \
-      hipLaunchKernelGGL(KERNEL<kRB>, __VA_ARGS__);               \
+    switch (kind) {                                               \
+      case kRF: hipLaunchKernelGGL(KERNEL<kRF>, __VA_ARGS__); break;       \
+      case kRB: hipLaunchKernelGGL(KERNEL<kRB>, __VA_ARGS__); break;       \
+      case kRBLin: hipLaunchKernelGGL(KERNEL<kRBLin>, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<kRFPc>, __VA_ARGS__); break;      \
+    }                                                             \
   } while (0)
 
 hipError_t launch_init_plain(const Tables& t, double* u, hipStream_t st) {
@@ -727,17 +732,22 @@ bool fused_fits(int tile) {
   return (int)attr.sharedSizeBytes <= max_lds;
 }
 
+template <int KIND>
+static void launch_fused_kind(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int tile,
+                              int halo, int nsub, dim3 g, dim3 b, hipStream_t st) {
+  if (tile == 1024) hipLaunchKernelGGL((k_step_fused<KIND, 4>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<KIND, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else hipLaunchKernelGGL((k_step_fused<KIND, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
+}
+
 hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
                              int tile, int halo, int nsub, int grid, hipStream_t st) {
   const dim3 g(grid), b(kBlock);
-  if (kind == kRF) {
-    if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRF, 4>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<kRF, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else hipLaunchKernelGGL((k_step_fused<kRF, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
-  } else {
-    if (tile == 1024) hipLaunchKernelGGL((k_step_fused<kRB, 4>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<kRB, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
-    else hipLaunchKernelGGL((k_step_fused<kRB, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  switch (kind) {
+    case kRF: launch_fused_kind<kRF>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
+    case kRB: launch_fused_kind<kRB>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
+    case kRBLin: launch_fused_kind<kRBLin>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
+    default: launch_fused_kind<kRFPc>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
   }
   return hipGetLastError();
 }
@@ -791,13 +801,14 @@ hipError_t launch_philox_fill(const uint32_t* ctr, uint32_t k0, uint32_t k1, uin
   return hipGetLastError();
 }
 
-hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int precision,
-                             const uint32_t* did, const int32_t* j, const int32_t* cell,
-                             const double* frac, double* out, int64_t n, hipStream_t st) {
+hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1, int32_t period,
+                             int precision, const uint32_t* did, const int32_t* j,
+                             const int32_t* cell, const double* frac, double* out, int64_t n,
+                             hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + kBlock - 1) / kBlock;
   QEW_KIND_DISPATCH(kind, k_force_eval, dim3((uint32_t)blocks), dim3(kBlock), 0, st, strength, k0, k1,
-                    precision, did, j, cell, frac, out, n);
+                    period, precision, did, j, cell, frac, out, n);
   return hipGetLastError();
 }
 

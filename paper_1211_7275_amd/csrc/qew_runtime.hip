@@ -68,7 +68,7 @@ struct GraphCache {
 
 struct qew_plan_s {
   // problem
-  int32_t S = 0, kind = 0, precision = 0, path = 0, k_req = 0, tile_req = 0, flags = 0;
+  int32_t S = 0, kind = 0, precision = 0, path = 0, k_req = 0, tile_req = 0, flags = 0, period = 0;
   double c = 0, dt = 0, strength = 0;
   uint64_t seed = 0;
   int64_t n_steps = 0;
@@ -200,9 +200,11 @@ Phys phys_of(const qew_plan_t* p) {
   ph.strength = p->strength;
   ph.cf = (float)p->c;
   ph.dtf = (float)p->dt;
-  ph.sgn_strf = p->kind == QEW_RF_CR_UNIFORM ? (float)p->strength : -(float)p->strength;
+  const bool force_values = p->kind == QEW_RF_CR_UNIFORM || p->kind == QEW_RF_PC_GAUSS;
+  ph.sgn_strf = force_values ? (float)p->strength : -(float)p->strength;
   ph.k0 = (uint32_t)(p->seed & 0xffffffffu);
   ph.k1 = (uint32_t)(p->seed >> 32);
+  ph.period = p->period;
   return ph;
 }
 
@@ -414,7 +416,8 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
   if (!pr) return fail(QEW_EINVAL, "problem is NULL");
   if (pr->n_samples < 1) return fail(QEW_EINVAL, "n_samples must be >= 1 (got %d)", pr->n_samples);
   if (!pr->L || !pr->f || !pr->disorder_id) return fail(QEW_EINVAL, "L, f and disorder_id must be non-NULL");
-  if (pr->kind != QEW_RF_CR_UNIFORM && pr->kind != QEW_RB_CR_GAUSS) return fail(QEW_EINVAL, "unknown disorder kind %d", pr->kind);
+  if (pr->kind < QEW_RF_CR_UNIFORM || pr->kind > QEW_RF_PC_GAUSS) return fail(QEW_EINVAL, "unknown disorder kind %d", pr->kind);
+  if (pr->period < 0 || pr->period >= (1 << 30)) return fail(QEW_EINVAL, "period must be in [0, 2^30)");
   if (!(std::isfinite(pr->c) && pr->c > 0)) return fail(QEW_EINVAL, "c must be finite and > 0");
   if (!(std::isfinite(pr->dt) && pr->dt > 0)) return fail(QEW_EINVAL, "dt must be finite and > 0");
   if (!(pr->c * pr->dt <= 0.5)) return fail(QEW_EINVAL, "c*dt = %g exceeds 1/2 (explicit Euler is unstable)", pr->c * pr->dt);
@@ -450,6 +453,7 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
   p->k_req = pr->k;
   p->tile_req = pr->tile;
   p->flags = pr->flags;
+  p->period = pr->period;
   p->c = pr->c;
   p->dt = pr->dt;
   p->strength = pr->strength;
@@ -806,18 +810,20 @@ qew_status qew_debug_philox_fill(const uint32_t* d_ctr, uint64_t seed, uint32_t*
   return QEW_OK;
 }
 
-qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, int32_t precision,
-                                const uint32_t* d_did, const int32_t* d_j, const int32_t* d_cell,
-                                const double* d_frac, double* d_out, int64_t N, void* stream) {
+qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, int32_t period,
+                                int32_t precision, const uint32_t* d_did, const int32_t* d_j,
+                                const int32_t* d_cell, const double* d_frac, double* d_out,
+                                int64_t N, void* stream) {
   g_err.clear();
-  if (kind != QEW_RF_CR_UNIFORM && kind != QEW_RB_CR_GAUSS) return fail(QEW_EINVAL, "unknown kind");
+  if (kind < QEW_RF_CR_UNIFORM || kind > QEW_RF_PC_GAUSS) return fail(QEW_EINVAL, "unknown kind");
+  if (period < 0 || period >= (1 << 30)) return fail(QEW_EINVAL, "bad period");
   if (precision != QEW_FP64_PLAIN && precision != QEW_FP32_SPLIT) return fail(QEW_EINVAL, "unknown precision");
   if (!(std::isfinite(strength) && strength >= 0)) return fail(QEW_EINVAL, "bad strength");
   if (N < 0) return fail(QEW_EINVAL, "N < 0");
   if (N > 0 && (!d_did || !d_j || !d_cell || !d_frac || !d_out)) return fail(QEW_EINVAL, "NULL device pointer");
   if (N > (int64_t(1) << 31) * 256) return fail(QEW_EINVAL, "N too large");
   QEW_HIP(launch_force_eval(kind, strength, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32),
-                            precision, d_did, d_j, d_cell, d_frac, d_out, N,
+                            period, precision, d_did, d_j, d_cell, d_frac, d_out, N,
                             static_cast<hipStream_t>(stream)));
   return QEW_OK;
 }

@@ -23,6 +23,8 @@ QEW_EUNSUPPORTED = -4
 
 QEW_RF_CR_UNIFORM = 0
 QEW_RB_CR_GAUSS = 1
+QEW_RB_LIN_GAUSS = 2
+QEW_RF_PC_GAUSS = 3
 QEW_FP64_PLAIN = 0
 QEW_FP32_SPLIT = 1
 QEW_ONE_STEP = 0
@@ -46,7 +48,7 @@ class qew_problem(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("n_steps", ctypes.c_int64),
         ("meas_steps", ctypes.POINTER(ctypes.c_int64)), ("n_meas", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("path", ctypes.c_int32), ("k", ctypes.c_int32),
-        ("tile", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("tile", ctypes.c_int32), ("flags", ctypes.c_int32), ("period", ctypes.c_int32),
     ]
 
 
@@ -94,7 +96,8 @@ def _load():
     lib.qew_debug_philox_fill.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_int64, vp]
     lib.qew_debug_philox_fill.restype = st
     lib.qew_debug_force_eval.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
-                                         ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
+                                         ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
+                                         ctypes.c_int64, vp]
     lib.qew_debug_force_eval.restype = st
     lib.qew_plan_destroy.argtypes = [vp]
     lib.qew_plan_destroy.restype = None
@@ -189,8 +192,8 @@ def qew_debug_philox_fill(d_ctr, seed, d_out, stream=None):
 
 
 def qew_debug_force_eval(kind, strength, seed, precision, d_did, d_j, d_cell, d_frac, d_out,
-                         stream=None):
-    _check(_lib.qew_debug_force_eval(int(kind), float(strength), int(seed), int(precision),
+                         stream=None, period=0):
+    _check(_lib.qew_debug_force_eval(int(kind), float(strength), int(seed), int(period), int(precision),
                                      d_did.data_ptr(), d_j.data_ptr(), d_cell.data_ptr(),
                                      d_frac.data_ptr(), d_out.data_ptr(), d_out.numel(),
                                      _stream_ptr(stream)), "qew_debug_force_eval")
@@ -232,7 +235,7 @@ def make_problem(p, precision=QEW_FP32_SPLIT, path=QEW_FUSED, k=0, tile=0, flags
         seed=int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, n_steps=int(p["n_steps"]),
         meas_steps=meas.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if meas.size else None,
         n_meas=meas.size, precision=int(precision), path=int(path), k=int(k), tile=int(tile),
-        flags=int(flags))
+        flags=int(flags), period=int(p.get("period", 0)))
     return pr, keep
 
 

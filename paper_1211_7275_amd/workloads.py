@@ -8,13 +8,16 @@ module holds none of the method's arithmetic (no generator of the disorder,
 no spline, no integrator).
 
 Problem dict keys: kind (0 = RF Catmull-Rom uniform, 1 = RB Catmull-Rom
-Gaussian), strength, seed, c, dt, n_steps, L [S], f [S], disorder_id [S],
-meas_steps [n_meas].
+Gaussian, 2 = RB linear-spline Gaussian, 3 = RF Gaussian without
+interpolation), strength, seed, c, dt, n_steps, L [S], f [S], disorder_id [S],
+meas_steps [n_meas], and optionally period (transverse period M, 0 = none).
 """
 import numpy as np
 
-RF = 0
-RB = 1
+RF = 0        # random field, uniform force values, Catmull-Rom
+RB = 1        # random bond, Gaussian potential, Catmull-Rom
+RB_LIN = 2    # random bond, Gaussian potential, linear spline (Case 3)
+RF_PC = 3     # random field, Gaussian forces, no interpolation (Case 4)
 
 SEED_BASE = 0x51EDC0DE00
 
@@ -97,7 +100,7 @@ def config4(kind, f_center, n_steps=1_000_000, n_meas=200, L=1 << 25, spacing=0.
 
 
 def custom(kind, L, f, n_steps, meas_steps, seed, disorder_id=None, c=1.0, dt=0.05,
-           strength=1.0):
+           strength=1.0, period=0):
     L = np.atleast_1d(np.asarray(L, np.int64))
     f = np.broadcast_to(np.asarray(f, np.float64), L.shape).copy()
     did = np.arange(L.size) if disorder_id is None else disorder_id
@@ -106,4 +109,5 @@ def custom(kind, L, f, n_steps, meas_steps, seed, disorder_id=None, c=1.0, dt=0.
         "c": float(c), "dt": float(dt), "n_steps": int(n_steps), "L": L, "f": f,
         "disorder_id": np.asarray(did, np.uint32),
         "meas_steps": np.asarray(meas_steps, np.int64),
+        "period": int(period),
     }

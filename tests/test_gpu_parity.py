@@ -86,20 +86,20 @@ def _force_points(n, rng):
     return j, cell, frac, did
 
 
-@pytest.mark.parametrize("kind", [0, 1])
-def test_force_eval_against_oracle(qew, oracle, kind):
+@pytest.mark.parametrize("kind,period", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 7), (2, 5)])
+def test_force_eval_against_oracle(qew, oracle, kind, period):
     import torch
     rng = np.random.default_rng(12 + kind)
     n = 20000
     j, cell, frac, did = _force_points(n, rng)
     for strength in (1.0, 0.7):
-        ref = np.array([oracle.pinning(kind, strength, SEED, did[i], j[i], float(cell[i]) + frac[i])
-                        for i in range(n)])
+        ref = np.array([oracle.pinning(kind, strength, SEED, did[i], j[i], float(cell[i]) + frac[i],
+                                       period) for i in range(n)])
         dev = [torch.from_numpy(x).cuda() for x in (did.view(np.int32), j, cell, frac)]
         for prec in (qew.QEW_FP64_PLAIN, qew.QEW_FP32_SPLIT):
-            say("force_eval kind", kind, "strength", strength, "precision", prec)
+            say("force_eval kind", kind, "period", period, "strength", strength, "precision", prec)
             out = torch.empty(n, dtype=torch.float64, device="cuda")
-            qew.qew_debug_force_eval(kind, strength, SEED, prec, *dev, out)
+            qew.qew_debug_force_eval(kind, strength, SEED, prec, *dev, out, period=period)
             torch.cuda.synchronize()
             got = out.cpu().numpy()
             err = np.abs(got - ref)
@@ -182,10 +182,10 @@ GEOMS = [(1, 1024), (5, 1024), (8, 1024), (16, 2048), (32, 2048), (32, 4096), (6
 SIZES = [3, 5, 31, 64, 100, 511, 1000, 1024, 1500, 5000]
 
 
-@pytest.mark.parametrize("kind", [0, 1])
-def test_fused_bit_identical_to_one_step(qew, kind):
+@pytest.mark.parametrize("kind,period", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 5)])
+def test_fused_bit_identical_to_one_step(qew, kind, period):
     p = workloads.custom(kind, SIZES, np.linspace(0.6, 1.4, len(SIZES)), 300,
-                         [0, 1, 2, 7, 33, 150, 299, 300], SEED + 5)
+                         [0, 1, 2, 7, 33, 150, 299, 300], SEED + 5, period=period)
     say("one-step split reference, kind", kind)
     ref = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP)
     for k, tile in GEOMS:
@@ -258,6 +258,89 @@ def test_random_bond_parity(qew, oracle):
     # v is compared relative to max(|v|, 1e-3) (absolute floor 1e-6).
     assert rel_err(b["v"], ref["v"], floor=1e-3) <= 1e-3
     assert rel_err(b["w2"], ref["w2"]) <= 1e-3
+
+
+# ------------------------------------------ Cases 3 and 4, transverse period --
+
+@pytest.mark.parametrize("kind", [2, 3])
+def test_discontinuous_disorder_parity(qew, oracle, kind):
+    """Case 3 (RB linear spline) and Case 4 (RF without interpolation) on the
+    small workload shape (L = 1024, 10^4 steps).
+
+    FP64: per site within 1e-10 of the oracle.  FP32 split: the force jumps at
+    the integers, so a trajectory is not a continuous function of its start:
+    the oracle itself, started 1e-7 away from the flat line, ends O(1) away at
+    most sites after a few hundred steps.  FP32 parity is therefore checked
+    (a) on the step map: from an FP32-representable state taken from the
+    oracle's run, one split step (one-step and fused paths) matches one oracle
+    Euler step per site within dt * 1e-4 (the FP32 force tolerance) plus four
+    FP32 ulps of the offset; (b) on the ensemble of 16 samples: the time
+    average of v over the last 90 % of the measurements and w2 at the end,
+    paired per sample with the oracle, differ by less than 5 standard errors
+    of the paired difference."""
+    N = 10_000
+    f = 1.6 if kind == 2 else 1.0
+    S = 16
+    meas = workloads.log_steps(N, 50)
+    p = workloads.custom(kind, [1024] * S, f, N, meas, SEED + 30 + kind)
+    say("oracle kind", kind, "16 x 1024, 10^4 steps")
+    ref = oracle.run(p)
+    say("fp64 plain kind", kind)
+    a = run_gpu(qew, p, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP)
+    e64 = max(np.max(np.abs(a["u"][s] - ref["u"][s])) for s in range(S))
+    say("  fp64 per-site err", e64)
+    assert e64 <= 1e-10
+    for key in ("v", "ubar", "w2"):
+        assert rel_err(a[key], ref[key], floor=1e-3) <= 1e-10
+
+    # (a) the FP32 split step map from the oracle's final states
+    pre = []
+    for s in range(4):
+        cell = np.floor(ref["u"][s])
+        r = (ref["u"][s] - cell).astype(np.float32)
+        r = np.where(r >= 1.0, np.nextafter(np.float32(1), np.float32(0)), r)
+        pre.append(cell + r.astype(np.float64))
+    p1 = workloads.custom(kind, [1024] * 4, f, N + 1, [N, N + 1], SEED + 30 + kind)
+    want = [oracle.euler(p["dt"], pre[s], oracle.forces(kind, 1.0, p1["seed"], s, 1.0, f, pre[s]))
+            for s in range(4)]
+    tol = p["dt"] * 1e-4 + 4 * 2.0 ** -24
+    for path in (qew.QEW_ONE_STEP, qew.QEW_FUSED):
+        sim = qew.Simulation(p1, precision=qew.QEW_FP32_SPLIT, path=path, k=8, tile=1024)
+        try:
+            for s in range(4):
+                sim.write_state(s, pre[s], N)
+            sim.run(resume=True)
+            got = [sim.read_state(s)[0] for s in range(4)]
+        finally:
+            sim.close()
+        err = max(np.max(np.abs(got[s] - want[s])) for s in range(4))
+        moved = np.mean(np.concatenate([np.floor(want[s]) != np.floor(pre[s]) for s in range(4)]))
+        say("  fp32 step map path", path, "max err", err, "sites changing cell", moved)
+        assert err <= tol
+
+    # (b) the FP32 split ensemble against the oracle's, paired per sample
+    say("fp32 split fused kind", kind)
+    b = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, states=False)
+    sel = meas >= N // 10
+    for name, qa, qb in (("v", b["v"][:, sel].mean(1), ref["v"][:, sel].mean(1)),
+                         ("w2", b["w2"][:, -1], ref["w2"][:, -1])):
+        d = qa - qb
+        t = abs(d.mean()) / (d.std(ddof=1) / np.sqrt(S))
+        say("  ensemble", name, qa.mean(), "oracle", qb.mean(), "paired t", t)
+        assert t <= 5.0
+
+
+def test_transverse_period_parity(qew, oracle):
+    """A medium periodic in u with M = 5 (sites wrap many times in 4000 steps):
+    FP64 per site within 1e-10 of the oracle, FP32 split within 1e-3."""
+    p = workloads.custom(0, [700, 1024], 1.0, 4000, workloads.log_steps(4000, 20), SEED + 40,
+                         period=5)
+    ref = oracle.run(p)
+    a = run_gpu(qew, p, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP)
+    assert max(np.max(np.abs(a["u"][s] - ref["u"][s])) for s in range(2)) <= 1e-10
+    b = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED)
+    assert max(np.max(np.abs(b["u"][s] - ref["u"][s])) for s in range(2)) <= 1e-3
+    assert min(ref["ubar"][:, -1]) > 3 * 5  # the line crossed the period several times
 
 
 # ----------------------------------------------------------- closed forms --

@@ -418,3 +418,23 @@ def test_transverse_period(oracle, kind):
         for u in (-3.25, 0.0, 0.5, 2.75, 6.9921875):  # dyadic, so u + M is exact
             assert oracle.pinning(kind, 1.0, SEED, 4, j, u, M) == oracle.pinning(kind, 1.0, SEED, 4, j, u + M, M)
     assert oracle.node(kind, SEED, 4, 5, 9) != oracle.node(kind, SEED, 4, 5, 2)
+
+
+@pytest.mark.parametrize("kind,f,chaotic", [(0, 1.0, False), (2, 1.6, True), (3, 1.0, True)])
+def test_sensitivity_to_the_start(oracle, kind, f, chaotic):
+    """With a C1 spline (Case 1) the Euler map is Lipschitz: a 1e-9 change of
+    the flat start stays ~1e-9 after 400 steps.  With a force that jumps at the
+    integers (Cases 3 and 4, Sec. IV C) a site that lands on the other side of
+    an integer gets an O(dt) different kick, and the difference spreads along
+    the chain: most sites end O(1) apart.  This is why FP32 runs of those cases
+    are compared with the oracle on the step map and on ensemble averages, not
+    site by site."""
+    rng = np.random.default_rng(3)
+    a = oracle.run_sample(kind, 1.0, 77, 0, 256, 1.0, 0.05, f, 400, [400])
+    b = oracle.run_sample(kind, 1.0, 77, 0, 256, 1.0, 0.05, f, 400, [400],
+                          u0=rng.uniform(-1, 1, 256) * 1e-9)
+    e = np.abs(a["u"] - b["u"])
+    if chaotic:
+        assert np.mean(e > 1e-3) > 0.5
+    else:
+        assert e.max() < 1e-8
