@@ -50,11 +50,17 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_fused_L2e22x4.md")
 
 
 def kernel_source_hash():
+    """sha256 (first 16 hex) of the kernel sources with comments and blank
+    space removed, so that a documentation edit keeps the measured traffic."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -206,12 +212,35 @@ def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
                              f"average {sum(d) / len(d):.5f} ms")
     counters = rows("*counter_collection.csv")
     if counters:
-        per = {}
+        # one record per dispatch: name, duration, counter sums
+        disp = {}
         for r in counters:
-            per.setdefault((short(r["Kernel_Name"]), r["Counter_Name"]), []).append(float(r["Counter_Value"]))
-        lines += ["", "| kernel | counter | dispatches | median per dispatch |", "|---|---|---|---|"]
-        for (k, c), v in sorted(per.items()):
-            lines.append(f"| `{k}` | {c} | {len(v)} | {statistics.median(v):.6g} |")
+            d = disp.setdefault(int(r["Dispatch_Id"]), {
+                "name": short(r["Kernel_Name"]),
+                "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), "c": {}})
+            d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        order = sorted(disp)
+        lines += ["", "Timed runs only (dispatches after the last initialisation kernel of each path):", "",
+                  "| kernel | counter | dispatches | median per dispatch | sum | kernel ms (sum) |",
+                  "|---|---|---|---|---|---|"]
+        for init, tag in (("k_init_split", "k_step_fused"), ("k_init_plain", "k_step_plain")):
+            inits = [i for i in order if init in disp[i]["name"]]
+            if not inits:
+                continue
+            seg = [disp[i] for i in order if i > inits[-1] and tag in disp[i]["name"]]
+            if not seg:
+                continue
+            ms = sum(d["ns"] for d in seg) / 1e6
+            for cn in sorted(seg[0]["c"]):
+                v = [d["c"].get(cn, 0.0) for d in seg]
+                lines.append(f"| `{seg[0]['name']}` | {cn} | {len(v)} | {statistics.median(v):.6g} "
+                             f"| {sum(v):.6g} | {ms:.3f} |")
+        copies = [d for d in disp.values() if "copyBuffer" in d["name"]]
+        if copies:
+            for cn in sorted(copies[0]["c"]):
+                v = [d["c"].get(cn, 0.0) for d in copies]
+                lines.append(f"| `{copies[0]['name']}` (runtime copies) | {cn} | {len(v)} "
+                             f"| {statistics.median(v):.6g} | {sum(v):.6g} | |")
     return "\n".join(lines)
 
 

@@ -9,15 +9,15 @@
 //                  Philox nodes regenerated per site update.  HBM traffic is
 //                  16 B per update (read u, write u; neighbours hit L1/L2).
 //   k_step_split1  the same on the split state (int32 cell + FP32 offset).
-//   k_step_fused   `nsub` split Euler steps per launch.  Each wave owns a tile
-//                  of 64*P consecutive sites held in registers (P per lane),
-//                  `halo` of them on each side recomputed redundantly, and
-//                  each site keeps the four nodes of its cell in registers
-//                  (and in HBM between launches).  A site whose cell changes
-//                  needs one new node; the wave gathers those requests into
-//                  LDS, generates them with all 64 lanes, and scatters them
-//                  back, so Philox costs about one wave pass per sub-step
-//                  instead of one per changed site slot.
+//   k_step_fused   `nsub` split Euler steps per launch.  Each workgroup owns
+//                  a tile of 256*P consecutive sites held in registers (P
+//                  per thread), `halo` of them on each side recomputed
+//                  redundantly; the four nodes of each site's cell stay in
+//                  LDS (and in HBM between launches).  A site whose cell
+//                  changes needs one new node; the workgroup gathers those
+//                  requests into LDS and generates them with all its lanes,
+//                  so Philox costs a fraction of a pass per sub-step instead
+//                  of one per changed site slot.
 //   k_meas_*       per-tile FP64 partials of sum F, sum (u-K), sum (u-K)^2.
 //   k_meas_final   per-sample combine (Chan et al. pairwise update) into
 //                  v, ubar, w2.
