@@ -193,3 +193,51 @@ def run(problem, u0=None, step0=0):
         states.append(r["u"])
     out["u"] = states
     return out
+
+
+# --------------------------------------------------------------------------
+# Structure factor, Eq. (6): S_q(t) = overbar |L^-1 sum_x u(x,t) e^{-iqx}|^2,
+# q = 2 pi n / L.  numpy's FFT is the library step; for real u the modes n and
+# L - n are equal, so n = 1 .. L/2 is returned.
+# --------------------------------------------------------------------------
+
+def structure_factor(u):
+    """S_n of one chain for n = 1 .. L//2 (index n - 1)."""
+    u = np.asarray(u, np.float64)
+    L = u.size
+    U = np.fft.rfft(u)
+    return (np.abs(U[1:L // 2 + 1]) / L) ** 2
+
+
+def sq_binned(S, edges):
+    """Mean of S_n over the modes n in [edges[b], edges[b+1]) for each bin b."""
+    edges = np.asarray(edges, np.int64)
+    return np.array([S[edges[b] - 1:edges[b + 1] - 1].mean() for b in range(edges.size - 1)])
+
+
+def states_at(problem, s, steps):
+    """States of sample s at the given increasing steps (flat start), by
+    running the chain segment by segment (the disorder does not depend on
+    time, so a continued run equals an uninterrupted one)."""
+    u = np.zeros(int(problem["L"][s]), np.float64)
+    out, now = [], 0
+    for m in steps:
+        if m > now:
+            u = run_sample(problem["kind"], problem["strength"], problem["seed"],
+                           problem["disorder_id"][s], problem["L"][s], problem["c"],
+                           problem["dt"], problem["f"][s], int(m) - now, [], u0=u,
+                           step0=now, period=problem.get("period", 0))["u"]
+            now = int(m)
+        out.append(u.copy())
+    return out
+
+
+def sq_series(problem, edges):
+    """Disorder-averaged binned S_q at every measurement step: [n_meas][n_bins]."""
+    meas = np.asarray(problem["meas_steps"], np.int64)
+    S = len(problem["L"])
+    acc = np.zeros((meas.size, len(edges) - 1))
+    for s in range(S):
+        for i, u in enumerate(states_at(problem, s, meas)):
+            acc[i] += sq_binned(structure_factor(u), edges)
+    return acc / S

@@ -438,3 +438,62 @@ def test_sensitivity_to_the_start(oracle, kind, f, chaotic):
         assert np.mean(e > 1e-3) > 0.5
     else:
         assert e.max() < 1e-8
+
+
+# ------------------------------------------------- structure factor, Eq. (6)
+
+@pytest.mark.parametrize("L", [8, 10, 16])
+def test_structure_factor_brute_force(oracle, L):
+    """S_n = |L^-1 sum_x u_x e^{-i 2 pi n x / L}|^2 written out as the sum of
+    squares of the cosine and sine sums, term by term."""
+    rng = np.random.default_rng(L)
+    u = rng.normal(size=L) * 3.0 + 7.0
+    S = oracle.structure_factor(u)
+    assert S.size == L // 2
+    for n in range(1, L // 2 + 1):
+        re = sum(u[x] * math.cos(2 * math.pi * n * x / L) for x in range(L)) / L
+        im = -sum(u[x] * math.sin(2 * math.pi * n * x / L) for x in range(L)) / L
+        assert S[n - 1] == pytest.approx(re * re + im * im, rel=1e-12, abs=1e-15)
+
+
+def test_structure_factor_parseval(oracle):
+    """Summed over n = 1 .. L-1 the structure factor is the width w2 of the
+    same chain (Parseval), computed here by the oracle's own two-pass sum."""
+    rng = np.random.default_rng(5)
+    for L in (64, 100, 4096):
+        u = np.cumsum(rng.normal(size=L)) + 1e4
+        S = oracle.structure_factor(u)
+        total = 2 * S.sum() - (S[-1] if L % 2 == 0 else 0.0)
+        _, _, w2 = oracle.measure(u, np.zeros(L))
+        assert total == pytest.approx(w2, rel=1e-11)
+
+
+def test_structure_factor_single_mode(oracle):
+    """u = A cos(2 pi k x / L + phi) + B has S_k = A^2 / 4 and nothing else;
+    the zone-boundary mode k = L/2 (u = A (-1)^x + B) has S = A^2."""
+    L, A, B = 256, 0.75, -3.0
+    x = np.arange(L)
+    for k in (1, 5, 127):
+        S = oracle.structure_factor(A * np.cos(2 * np.pi * k * x / L + 0.3) + B)
+        assert S[k - 1] == pytest.approx(A * A / 4, rel=1e-12)
+        assert np.delete(S, k - 1).max() < 1e-26  # rounding of the cosines
+    S = oracle.structure_factor(A * (-1.0) ** x + B)
+    assert S[-1] == pytest.approx(A * A, rel=1e-13)
+    assert S[:-1].max() < 1e-26
+
+
+def test_structure_factor_of_a_relaxing_mode(oracle):
+    """No disorder, start u = A cos(2 pi k x / L): each Euler step multiplies
+    the mode by 1 - 4 c dt sin^2(pi k / L), so S_k(m) = A^2 lambda^(2m) / 4
+    while the line drifts at v = f (which S_q does not see)."""
+    L, k, A, c, dt, f = 128, 3, 2.0, 1.0, 0.05, 0.7
+    lam = 1 - 4 * c * dt * math.sin(math.pi * k / L) ** 2
+    u0 = A * np.cos(2 * np.pi * k * np.arange(L) / L)
+    u = u0
+    for m in (0, 1, 50, 400):
+        if m:
+            u = oracle.run_sample(oracle.RF, 0.0, SEED, 0, L, c, dt, f, m - prev, [], u0=u)["u"]
+        prev = m
+        S = oracle.structure_factor(u)
+        assert S[k - 1] == pytest.approx(A * A * lam ** (2 * m) / 4, rel=1e-10)
+        assert np.delete(S, k - 1).max() < 1e-20
