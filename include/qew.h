@@ -101,6 +101,13 @@ typedef struct qew_problem {
   int32_t         flags;        /* QEW_FLAG_* bits                                      */
   int32_t         period;       /* transverse period M of the disorder in u (node n is
                                    node n mod M); 0 = no period; else 1 <= M < 2^30     */
+  int32_t         sq_bins;      /* structure factor S_q (Eq. (6)) at every measurement:
+                                   number of mode bins; 0 = off.  Needs every L_s equal,
+                                   a power of two, 8 <= L <= 2^30                        */
+  const int64_t  *sq_edges;     /* [sq_bins + 1] host, read only in qew_plan: bin b holds
+                                   the modes n in [sq_edges[b], sq_edges[b+1]), q = 2 pi
+                                   n / L; strictly increasing, 1 <= sq_edges[0],
+                                   sq_edges[sq_bins] <= L/2 + 1                          */
 } qew_problem;
 
 typedef struct qew_plan_s qew_plan_t;
@@ -178,6 +185,17 @@ qew_status qew_run(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *stream, 
  * not yet taken are NaN.  Synchronous.
  */
 qew_status qew_ensemble(const qew_plan_t *plan, const void *d_ws, void *stream, double *h_out);
+
+/*
+ * Structure factor of Eq. (6), S_q(t) = overbar |L^-1 sum_x u(x,t) e^{-iqx}|^2
+ * with q = 2 pi n / L, computed on the device in FP64 at every measurement
+ * step of the runs so far (problem.sq_bins > 0, else QEW_EINVAL).  h_sq is a
+ * host array [n_meas][sq_bins]: entry (m, b) is the mean over the samples and
+ * over the modes n of bin b (modes n and L - n are equal for a real line, so
+ * the bins cover 1 <= n <= L/2).  Entries of measurements not yet taken are
+ * NaN.  Synchronous.
+ */
+qew_status qew_sq_get(const qew_plan_t *plan, const void *d_ws, void *stream, double *h_sq);
 
 /* Statistics of the last qew_run of this plan (host pointer). */
 qew_status qew_run_stats_get(const qew_plan_t *plan, qew_run_stats *stats);

@@ -225,7 +225,7 @@ def states_at(problem, s, steps):
         if m > now:
             u = run_sample(problem["kind"], problem["strength"], problem["seed"],
                            problem["disorder_id"][s], problem["L"][s], problem["c"],
-                           problem["dt"], problem["f"][s], int(m) - now, [], u0=u,
+                           problem["dt"], problem["f"][s], int(m), [], u0=u,
                            step0=now, period=problem.get("period", 0))["u"]
             now = int(m)
         out.append(u.copy())

@@ -78,4 +78,11 @@ hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1
                              const uint32_t* did, const int32_t* j, const int32_t* cell,
                              const double* frac, double* out, int64_t n, hipStream_t st);
 
+// Structure factor at one measurement: pack, FFT passes, per-mode |U_n/L|^2,
+// binned mean over samples into out[n_bins].  Every L_s equals L (power of
+// two); u_plain != nullptr selects the FP64 state, else `split`.
+hipError_t launch_sq(const int64_t* off, int S, int64_t L, const double* u_plain, SplitBuf split,
+                     double2* bufA, double2* bufB, const int64_t* edges, int n_bins, double* out,
+                     hipStream_t st);
+
 }  // namespace qew

@@ -52,9 +52,9 @@ constexpr int kTuneK[3] = {8, 16, 32};
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t err, off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len;
+  size_t err, off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len, sq_edges;
   size_t tables_end;
-  size_t part, series, ens, stA0, stA1, stB0, stB1, ndA, ndB;
+  size_t part, series, ens, sq_series, fftA, fftB, stA0, stA1, stB0, stB1, ndA, ndB;
   size_t total;
 };
 
@@ -69,6 +69,8 @@ struct GraphCache {
 struct qew_plan_s {
   // problem
   int32_t S = 0, kind = 0, precision = 0, path = 0, k_req = 0, tile_req = 0, flags = 0, period = 0;
+  int32_t sq_bins = 0;
+  std::vector<int64_t> sq_edges;
   double c = 0, dt = 0, strength = 0;
   uint64_t seed = 0;
   int64_t n_steps = 0;
@@ -146,10 +148,19 @@ void compute_layout(qew_plan_t* p) {
   l.ft_s = take(nft * 4);
   l.ft_p0 = take(nft * 4);
   l.ft_len = take(nft * 4);
+  l.sq_edges = take(p->sq_edges.size() * 8);
   l.tables_end = o;
   l.part = take(nmt * sizeof(Partial));
   l.series = take(S * std::max<size_t>(p->meas.size(), 1) * 3 * 8);
   l.ens = take(7 * std::max<size_t>(p->meas.size(), 1) * 8);
+  if (p->sq_bins > 0) {
+    const size_t half = (size_t)(p->L[0] / 2);
+    l.sq_series = take(std::max<size_t>(p->meas.size(), 1) * p->sq_bins * 8);
+    l.fftA = take(S * half * 16);
+    l.fftB = take(S * half * 16);
+  } else {
+    l.sq_series = l.fftA = l.fftB = 0;
+  }
   const size_t n = (size_t)p->padded;
   if (p->precision == QEW_FP64_PLAIN) {
     l.stA0 = take(n * 8);
@@ -247,6 +258,7 @@ std::vector<char> table_image(const qew_plan_t* p) {
   put(l.ft_s, p->ft_s.data(), p->ft_s.size() * 4);
   put(l.ft_p0, p->ft_p0.data(), p->ft_p0.size() * 4);
   put(l.ft_len, p->ft_len.data(), p->ft_len.size() * 4);
+  put(l.sq_edges, p->sq_edges.data(), p->sq_edges.size() * 8);
   return img;
 }
 
@@ -265,6 +277,9 @@ double* series_of(const qew_plan_t* p, void* ws) {
 qew_status clear_series(const qew_plan_t* p, void* ws, hipStream_t st) {
   QEW_HIP(launch_fill_f64(series_of(p, ws), (int64_t)p->S * (int64_t)p->meas.size() * 3,
                           __builtin_nan(""), st));
+  if (p->sq_bins > 0)
+    QEW_HIP(launch_fill_f64(reinterpret_cast<double*>(static_cast<char*>(ws) + p->lay.sq_series),
+                            (int64_t)p->meas.size() * p->sq_bins, __builtin_nan(""), st));
   return QEW_OK;
 }
 
@@ -386,6 +401,15 @@ qew_status measure(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
   else
     QEW_HIP(launch_meas_split(t, split_buf(p, ws, p->cur_buf), ph, p->kind, part, st));
   QEW_HIP(launch_meas_final(t, p->S, part, mi, (int)p->meas.size(), series, st));
+  if (p->sq_bins > 0) {
+    char* b = static_cast<char*>(ws);
+    const bool plain = p->precision == QEW_FP64_PLAIN;
+    QEW_HIP(launch_sq(t.off, p->S, p->L[0], plain ? plain_buf(p, ws, p->cur_buf) : nullptr,
+                      plain ? SplitBuf{} : split_buf(p, ws, p->cur_buf),
+                      reinterpret_cast<double2*>(b + p->lay.fftA), reinterpret_cast<double2*>(b + p->lay.fftB),
+                      reinterpret_cast<const int64_t*>(b + p->lay.sq_edges), p->sq_bins,
+                      reinterpret_cast<double*>(b + p->lay.sq_series) + (size_t)mi * p->sq_bins, st));
+  }
   p->stats.meas_launches++;
   return QEW_OK;
 }
@@ -439,6 +463,19 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
     return fail(QEW_EINVAL, "tile must be 0, 1024, 2048 or 4096");
   if (pr->k > 0 && pr->tile > 0 && 4 * pr->k > pr->tile) return fail(QEW_EINVAL, "need 4*k <= tile");
   if (pr->flags & ~(QEW_FLAG_NO_GRAPH | QEW_FLAG_TIMING)) return fail(QEW_EINVAL, "unknown flag bits");
+  if (pr->sq_bins < 0) return fail(QEW_EINVAL, "sq_bins must be >= 0");
+  if (pr->sq_bins > 0) {
+    if (!pr->sq_edges) return fail(QEW_EINVAL, "sq_edges is NULL");
+    const int64_t L0 = pr->L[0];
+    if (L0 < 8 || L0 > kMaxL || (L0 & (L0 - 1)) != 0)
+      return fail(QEW_EINVAL, "the structure factor needs a power-of-two L in [8, 2^30] (got %lld)", (long long)L0);
+    for (int32_t s = 1; s < pr->n_samples; ++s)
+      if (pr->L[s] != L0) return fail(QEW_EINVAL, "the structure factor needs equal L for every sample");
+    if (pr->sq_edges[0] < 1) return fail(QEW_EINVAL, "sq_edges[0] must be >= 1");
+    for (int32_t b = 0; b < pr->sq_bins; ++b)
+      if (pr->sq_edges[b + 1] <= pr->sq_edges[b]) return fail(QEW_EINVAL, "sq_edges must be strictly increasing (index %d)", b + 1);
+    if (pr->sq_edges[pr->sq_bins] > L0 / 2 + 1) return fail(QEW_EINVAL, "sq_edges[%d] exceeds L/2 + 1", pr->sq_bins);
+  }
   for (int32_t s = 0; s < pr->n_samples; ++s) {
     if (pr->L[s] < 3 || pr->L[s] > kMaxL) return fail(QEW_EINVAL, "L[%d] = %lld outside [3, 2^30]", s, (long long)pr->L[s]);
     if (!std::isfinite(pr->f[s])) return fail(QEW_EINVAL, "f[%d] is not finite", s);
@@ -454,6 +491,8 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
   p->tile_req = pr->tile;
   p->flags = pr->flags;
   p->period = pr->period;
+  p->sq_bins = pr->sq_bins;
+  if (pr->sq_bins > 0) p->sq_edges.assign(pr->sq_edges, pr->sq_edges + pr->sq_bins + 1);
   p->c = pr->c;
   p->dt = pr->dt;
   p->strength = pr->strength;
@@ -726,6 +765,19 @@ qew_status qew_ensemble(const qew_plan_t* p, const void* ws, void* stream, doubl
   double* ens = reinterpret_cast<double*>(static_cast<char*>(w) + p->lay.ens);
   QEW_HIP(launch_ensemble(p->S, n_meas, series_of(p, w), ens, st));
   QEW_HIP(hipMemcpyAsync(h_out, ens, (size_t)7 * n_meas * 8, hipMemcpyDeviceToHost, st));
+  QEW_HIP(hipStreamSynchronize(st));
+  return QEW_OK;
+}
+
+qew_status qew_sq_get(const qew_plan_t* p, const void* ws, void* stream, double* h_sq) {
+  g_err.clear();
+  if (!p || !ws || !h_sq) return fail(QEW_EINVAL, "plan, workspace and h_sq must be non-NULL");
+  if (p->sq_bins <= 0) return fail(QEW_EINVAL, "the problem has no structure factor bins");
+  if (p->state_ws != ws) return fail(QEW_EINVAL, "this workspace holds no run of this plan");
+  const size_t n = p->meas.size() * (size_t)p->sq_bins;
+  if (n == 0) return QEW_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  QEW_HIP(hipMemcpyAsync(h_sq, static_cast<const char*>(ws) + p->lay.sq_series, n * 8, hipMemcpyDeviceToHost, st));
   QEW_HIP(hipStreamSynchronize(st));
   return QEW_OK;
 }

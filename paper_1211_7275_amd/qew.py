@@ -33,7 +33,7 @@ QEW_FLAG_NO_GRAPH = 1
 QEW_FLAG_TIMING = 2
 
 EXPORTS = ("qew_plan", "qew_workspace_bytes", "qew_plan_info_get", "qew_autotune", "qew_run",
-           "qew_ensemble", "qew_run_stats_get", "qew_read_state", "qew_write_state",
+           "qew_ensemble", "qew_sq_get", "qew_run_stats_get", "qew_read_state", "qew_write_state",
            "qew_debug_philox_fill", "qew_debug_force_eval", "qew_plan_destroy", "qew_last_error")
 
 ENSEMBLE_ROWS = ("v", "v_se", "w2", "w2_se", "ubar", "ubar_se", "w2_about_ensemble_ubar")
@@ -49,6 +49,7 @@ class qew_problem(ctypes.Structure):
         ("meas_steps", ctypes.POINTER(ctypes.c_int64)), ("n_meas", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("path", ctypes.c_int32), ("k", ctypes.c_int32),
         ("tile", ctypes.c_int32), ("flags", ctypes.c_int32), ("period", ctypes.c_int32),
+        ("sq_bins", ctypes.c_int32), ("sq_edges", ctypes.POINTER(ctypes.c_int64)),
     ]
 
 
@@ -87,6 +88,8 @@ def _load():
     lib.qew_run.restype = st
     lib.qew_ensemble.argtypes = [vp, vp, vp, dp]
     lib.qew_ensemble.restype = st
+    lib.qew_sq_get.argtypes = [vp, vp, vp, dp]
+    lib.qew_sq_get.restype = st
     lib.qew_run_stats_get.argtypes = [vp, ctypes.POINTER(qew_run_stats)]
     lib.qew_run_stats_get.restype = st
     lib.qew_read_state.argtypes = [vp, vp, vp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64)]
@@ -164,6 +167,13 @@ def qew_ensemble(plan, ws, n_meas, stream=None):
     return dict(zip(ENSEMBLE_ROWS, out))
 
 
+def qew_sq_get(plan, ws, n_meas, n_bins, stream=None):
+    """Disorder-averaged binned structure factor [n_meas][n_bins] (Eq. (6))."""
+    out = np.zeros((int(n_meas), int(n_bins)), np.float64)
+    _check(_lib.qew_sq_get(plan, ws.data_ptr(), _stream_ptr(stream), _dptr(out)), "qew_sq_get")
+    return out
+
+
 def qew_run_stats_get(plan):
     s = qew_run_stats()
     _check(_lib.qew_run_stats_get(plan, ctypes.byref(s)), "qew_run_stats_get")
@@ -225,7 +235,9 @@ def make_problem(p, precision=QEW_FP32_SPLIT, path=QEW_FUSED, k=0, tile=0, flags
     f = np.ascontiguousarray(p["f"], np.float64)
     did = np.ascontiguousarray(p["disorder_id"], np.uint32)
     meas = np.ascontiguousarray(p["meas_steps"], np.int64)
-    keep = (L, f, did, meas)
+    edges = p.get("sq_edges")
+    edges = None if edges is None else np.ascontiguousarray(edges, np.int64)
+    keep = (L, f, did, meas, edges)
     pr = qew_problem(
         n_samples=L.size, kind=int(p["kind"]),
         L=L.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -235,7 +247,9 @@ def make_problem(p, precision=QEW_FP32_SPLIT, path=QEW_FUSED, k=0, tile=0, flags
         seed=int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, n_steps=int(p["n_steps"]),
         meas_steps=meas.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if meas.size else None,
         n_meas=meas.size, precision=int(precision), path=int(path), k=int(k), tile=int(tile),
-        flags=int(flags), period=int(p.get("period", 0)))
+        flags=int(flags), period=int(p.get("period", 0)),
+        sq_bins=0 if edges is None else edges.size - 1,
+        sq_edges=None if edges is None else edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     return pr, keep
 
 
@@ -253,6 +267,8 @@ class Simulation:
         self.ws = self.ws[off: off + nbytes]
         self.S = len(problem["L"])
         self.n_meas = len(problem["meas_steps"])
+        edges = problem.get("sq_edges")
+        self.sq_bins = 0 if edges is None else len(edges) - 1
 
     def close(self):
         if self.plan:
@@ -284,6 +300,10 @@ class Simulation:
     def ensemble(self, stream=None):
         """Disorder average and standard errors of the series (computed on the device)."""
         return qew_ensemble(self.plan, self.ws, self.n_meas, stream)
+
+    def structure_factor(self, stream=None):
+        """Binned S_q averaged over samples at every measurement: [n_meas][sq_bins]."""
+        return qew_sq_get(self.plan, self.ws, self.n_meas, self.sq_bins, stream)
 
     def stats(self):
         return qew_run_stats_get(self.plan)

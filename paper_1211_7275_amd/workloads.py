@@ -10,7 +10,8 @@ no spline, no integrator).
 Problem dict keys: kind (0 = RF Catmull-Rom uniform, 1 = RB Catmull-Rom
 Gaussian, 2 = RB linear-spline Gaussian, 3 = RF Gaussian without
 interpolation), strength, seed, c, dt, n_steps, L [S], f [S], disorder_id [S],
-meas_steps [n_meas], and optionally period (transverse period M, 0 = none).
+meas_steps [n_meas], and optionally period (transverse period M, 0 = none)
+and sq_edges (mode bins of the structure factor, see sq_edges_full / sq_edges_log).
 """
 import numpy as np
 
@@ -99,8 +100,30 @@ def config4(kind, f_center, n_steps=1_000_000, n_meas=200, L=1 << 25, spacing=0.
                     SEED_BASE + 4 + int(kind))
 
 
+def sq_edges_full(L):
+    """One structure-factor bin per mode n = 1 .. L/2."""
+    return np.arange(1, int(L) // 2 + 2, dtype=np.int64)
+
+
+def sq_edges_log(L, n_bins):
+    """At most n_bins bins of the modes 1 .. L/2, log-spaced, distinct integer edges."""
+    top = int(L) // 2 + 1
+    e = np.unique(np.round(np.logspace(0, np.log10(top), int(n_bins) + 1)).astype(np.int64))
+    e[0], e[-1] = 1, top
+    return np.unique(e)
+
+
+def config_sq(n_steps=10_000, n_meas=30, samples=64, L=8192, f=1.0, kind=RF):
+    """Structure factor during relaxation at the shape of Fig. 4 (L = 8192), with a
+    smaller ensemble: every mode n = 1 .. L/2 at log-spaced times."""
+    p = _problem(kind, [L] * samples, [f] * samples, np.arange(samples), n_steps, n_meas,
+                 SEED_BASE + 8)
+    p["sq_edges"] = sq_edges_full(L)
+    return p
+
+
 def custom(kind, L, f, n_steps, meas_steps, seed, disorder_id=None, c=1.0, dt=0.05,
-           strength=1.0, period=0):
+           strength=1.0, period=0, sq_edges=None):
     L = np.atleast_1d(np.asarray(L, np.int64))
     f = np.broadcast_to(np.asarray(f, np.float64), L.shape).copy()
     did = np.arange(L.size) if disorder_id is None else disorder_id
@@ -110,4 +133,5 @@ def custom(kind, L, f, n_steps, meas_steps, seed, disorder_id=None, c=1.0, dt=0.
         "disorder_id": np.asarray(did, np.uint32),
         "meas_steps": np.asarray(meas_steps, np.int64),
         "period": int(period),
+        "sq_edges": None if sq_edges is None else np.asarray(sq_edges, np.int64),
     }

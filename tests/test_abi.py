@@ -138,3 +138,31 @@ def test_run_rejects_small_or_missing_workspace():
         assert lib.qew_debug_philox_fill(None, 0, None, 5, None) == qew.QEW_EINVAL
     finally:
         qew.qew_plan_destroy(plan)
+
+
+def test_plan_structure_factor_options():
+    """S_q needs equal power-of-two lengths and valid mode bins; it adds the
+    FFT buffers and the [n_meas][bins] series to the workspace."""
+    good = workloads.custom(0, [64, 64], 1.0, 100, [0, 10, 100], 123, sq_edges=[1, 2, 5, 33])
+    assert _plan_status(good)[0] == 0
+    assert _plan_status(good, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_ONE_STEP)[0] == 0
+    for L, edges in (([64, 32], [1, 5]),          # unequal lengths
+                     ([48, 48], [1, 5]),          # not a power of two
+                     ([4, 4], [1, 2]),            # below 8
+                     ([64, 64], [0, 5]),          # mode 0
+                     ([64, 64], [1, 34]),         # beyond L/2 + 1
+                     ([64, 64], [1, 5, 5]),       # empty bin
+                     ([64, 64], [3, 2])):         # decreasing
+        bad = workloads.custom(0, L, 1.0, 100, [0, 10, 100], 123, sq_edges=edges)
+        st, msg = _plan_status(bad)
+        assert st == qew.QEW_EINVAL and msg, (L, edges)
+    plain = workloads.custom(0, [1024] * 3, 1.0, 100, [0, 10, 100], 123)
+    with_sq = dict(plain, sq_edges=workloads.sq_edges_full(1024))
+    sizes = []
+    for p in (plain, with_sq):
+        pr, keep = qew.make_problem(p, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_ONE_STEP)
+        h = qew.qew_plan(pr)
+        sizes.append(qew.qew_workspace_bytes(h))
+        qew.qew_plan_destroy(h)
+    # two complex FP64 buffers of L/2 per sample, plus 3 x 513 bins
+    assert sizes[1] - sizes[0] >= 2 * 3 * 512 * 16 + 3 * 513 * 8

@@ -508,3 +508,85 @@ def test_edge_cases(qew):
     out = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=8, tile=1024)
     assert out["v"].shape == (1, 0)
     assert np.all(np.isfinite(out["u"][0]))
+
+
+# ------------------------------------------------ structure factor, Eq. (6)
+
+def _sq_gpu(qew, p, precision, path, states=None, step=0, k=0, tile=0):
+    """Run p (or measure the given states at `step`) and return (S_q, series)."""
+    sim = qew.Simulation(p, precision=precision, path=path, k=k, tile=tile)
+    try:
+        if states is not None:
+            for s, u in enumerate(states):
+                sim.write_state(s, u, step)
+            out = sim.run(resume=True)
+        else:
+            out = sim.run()
+        return sim.structure_factor(), out
+    finally:
+        sim.close()
+
+
+def test_structure_factor_parity(qew, oracle):
+    """Every mode n = 1 .. L/2 of a relaxing RF line (L = 1024 x 4) at six
+    times against the oracle's FFT of its own trajectory; Parseval against the
+    library's own w2; exactly zero on the flat start."""
+    L = 1024
+    edges = workloads.sq_edges_full(L)
+    meas = [0, 1, 10, 100, 1000, 2000]
+    p = workloads.custom(0, [L] * 4, 1.0, 2000, meas, SEED + 50, sq_edges=edges)
+    say("oracle S_q, L=1024 x 4, 2000 steps")
+    ref = oracle.sq_series(p, edges)
+    for prec, path, rtol, floor in ((qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 1e-9, 1e-12),
+                                    (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 1e-2, 1e-6)):
+        say("gpu S_q", prec, path)
+        got, out = _sq_gpu(qew, p, prec, path, k=16, tile=1024)
+        assert got.shape == (len(meas), L // 2)
+        assert np.all(got[0] == 0.0)
+        for m in range(1, len(meas)):
+            err = np.abs(got[m] - ref[m])
+            tol = rtol * ref[m] + floor * ref[m].max()
+            say("  step", meas[m], "max rel err", float(np.max(err / np.maximum(ref[m], 1e-300))))
+            assert np.all(err <= tol)
+            parseval = 2 * got[m][:-1].sum() + got[m][-1]
+            assert parseval == pytest.approx(out["w2"][:, m].mean(), rel=1e-10 if prec == 0 else 1e-6)
+
+
+def test_structure_factor_relaxing_mode(qew):
+    """No disorder, start u = A cos(2 pi k x / L) + B: S_k(m) = A^2 lambda^(2m) / 4
+    with lambda = 1 - 4 c dt sin^2(pi k / L); every other mode stays ~0."""
+    L, k, A, B = 4096, 7, 1.5, 12.25
+    lam = 1 - 4 * 1.0 * 0.05 * np.sin(np.pi * k / L) ** 2
+    x = np.arange(L)
+    u0 = A * np.cos(2 * np.pi * k * x / L) + B  # the split state rounds its offsets to FP32
+    meas = [0, 1, 100, 1000]
+    p = workloads.custom(0, [L, L], 0.3, 1000, meas, SEED, strength=0.0,
+                         sq_edges=workloads.sq_edges_full(L))
+    for prec, path, rtol in ((qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 1e-9),
+                             (qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP, 1e-4)):
+        got, _ = _sq_gpu(qew, p, prec, path, states=[u0, u0], step=0)
+        for i, m in enumerate(meas):
+            want = A * A * lam ** (2 * m) / 4
+            assert got[i][k - 1] == pytest.approx(want, rel=rtol)
+            assert np.delete(got[i], k - 1).max() < (1e-20 if prec == 0 else 1e-9)
+
+
+@pytest.mark.parametrize("L,samples", [(1 << 22, 2), (1 << 25, 1)])
+def test_structure_factor_full_size(qew, oracle, L, samples):
+    """Chains of 2^22 and 2^25 sites (the largest workloads) holding seeded
+    rough lines (random walks with FP32-representable offsets), measured in
+    both precisions: 64 log-spaced mode bins against the oracle's FFT."""
+    rng = np.random.default_rng(L)
+    states = []
+    for _ in range(samples):
+        u = np.cumsum(rng.normal(size=L)) * 0.01 + 50.0
+        states.append(np.floor(u) + (u - np.floor(u)).astype(np.float32))
+    edges = workloads.sq_edges_log(L, 64)
+    want = np.mean([oracle.sq_binned(oracle.structure_factor(u), edges) for u in states], axis=0)
+    p = workloads.custom(0, [L] * samples, 1.0, 0, [0], SEED, sq_edges=edges)
+    for prec in (qew.QEW_FP64_PLAIN, qew.QEW_FP32_SPLIT):
+        say("S_q full size", L, samples, "precision", prec)
+        got, _ = _sq_gpu(qew, p, prec, qew.QEW_ONE_STEP, states=states, step=0)
+        rel = np.abs(got[0] - want) / want
+        say("  max rel err", float(rel.max()))
+        assert rel.max() <= 1e-9

@@ -14,6 +14,7 @@ import pytest
 from scipy import stats
 
 from tests import philox_blackbox
+from paper_1211_7275_amd import workloads
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 SEED = 0x51EDC0DE00
@@ -497,3 +498,12 @@ def test_structure_factor_of_a_relaxing_mode(oracle):
         S = oracle.structure_factor(u)
         assert S[k - 1] == pytest.approx(A * A * lam ** (2 * m) / 4, rel=1e-10)
         assert np.delete(S, k - 1).max() < 1e-20
+
+
+def test_states_at_equals_uninterrupted_runs(oracle):
+    """The segment-by-segment states used for S_q equal single runs to each step."""
+    p = workloads.custom(0, [96], 1.1, 50, [0, 1, 7, 50], SEED + 3)
+    got = oracle.states_at(p, 0, [0, 1, 7, 50])
+    for m, u in zip([0, 1, 7, 50], got):
+        ref = oracle.run_sample(0, 1.0, p["seed"], 0, 96, 1.0, 0.05, 1.1, m, [])["u"]
+        assert np.array_equal(u, ref)
