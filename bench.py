@@ -29,7 +29,9 @@ from paper_1211_7275_amd import workloads  # noqa: E402
 # MI355X (gfx950) figures used for the rooflines.
 CUS = 256
 CLOCK_HZ = 2.4e9
-VALU_LANE_OPS = CUS * 4 * 16 * CLOCK_HZ     # 4 SIMD x 16 lanes per CU per clock = 39.3e12
+# FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMAs/s: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
+# 32-bit VALU lane-operations per second.
+VALU_LANE_OPS = CUS * 4 * 32 * CLOCK_HZ
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic VALU operations of one FP32 split site update:
@@ -244,6 +246,42 @@ def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
     return "\n".join(lines)
 
 
+# Workloads besides the benchmark line: name -> (description, builder(steps)).
+# The drives of the L = 2^25 workloads sit at the critical force bracketed by
+# the f-scan of `paper_1211_7275_amd.std` (L = 2^16, 10^5 steps).
+FC_SCAN = {0: 1.00, 1: 1.00}
+OTHER_WORKLOADS = {
+    "c1": ("L=2^16 RB Catmull-Rom Gaussian, 64 disorders x f in {0.8, 1.0, 1.2}",
+           lambda n: workloads.config1(n_steps=n)),
+    "c2": ("512 RF samples, L_s = 2^10..2^16 (uneven batch), f=1.0",
+           lambda n: workloads.config2(n_steps=n)),
+    "c4rf": ("L=2^25 x 5 drives around f_c, RF Catmull-Rom uniform, one disorder",
+             lambda n: workloads.config4(0, FC_SCAN[0], n_steps=n)),
+    "c4rb": ("L=2^25 x 5 drives around f_c, RB Catmull-Rom Gaussian, one disorder",
+             lambda n: workloads.config4(1, FC_SCAN[1], n_steps=n)),
+}
+
+
+def other_workload(qew, args):
+    desc, build = OTHER_WORKLOADS[args.workload]
+    steps = args.steps
+    p = build(steps)
+    out, st, info, wall = time_path(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, args.warmup,
+                                    k=args.k, tile=args.tile)
+    value = info.total_sites * steps / wall
+    roof = fused_roofline(p["kind"], st, info, out, steps)
+    roof["traffic"] = None  # the committed traffic summary covers the benchmark workload only
+    return {"metric": "site-updates/s (FP32 split, fused)", "value": round(value, 1),
+            "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "ms_per_step": round(wall * 1e3 / steps, 6), "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{args.workload}: {desc}", "samples": len(p["L"]),
+                       "total_sites": int(info.total_sites),
+                       "measurements": int(len(p["meas_steps"])), "k": info.k, "tile": info.tile},
+            "roofline": roof,
+            "v_last_mean": float(np.nanmean(out["v"][:, -1])) if out["v"].shape[1] else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +299,9 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output under DIR and exit")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--workload", default="c3", choices=sorted(OTHER_WORKLOADS) + ["c3"],
+                    help="c3 (default): the benchmark line; others print one line for that "
+                         "workload's FP32 split fused throughput (--steps sets the horizon)")
     args = ap.parse_args()
 
     if args.summarize_profile:
@@ -289,6 +330,10 @@ def main():
         return
 
     from paper_1211_7275_amd import qew
+
+    if args.workload != "c3":
+        print(json.dumps(other_workload(qew, args)), flush=True)
+        return
 
     p = bench_problem(args.steps)
     out, st, info, wall = time_path(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, args.warmup,

@@ -590,3 +590,23 @@ def test_structure_factor_full_size(qew, oracle, L, samples):
         rel = np.abs(got[0] - want) / want
         say("  max rel err", float(rel.max()))
         assert rel.max() <= 1e-9
+
+
+# ------------------------------------------------------ STD f-scan (Sec. IV)
+
+def test_fscan_gpu_matches_oracle(qew, oracle):
+    """The batched f-scan through the library classifies every drive as the
+    oracle's series of the same problem do (FP64 plain path)."""
+    from paper_1211_7275_amd import std
+    drives = np.array([0.3, 0.9, 1.2, 2.0])
+    n, pts, L = 20_000, 40, 256
+    r = std.fscan(0, L, drives, n, pts, SEED + 60, disorders=2, precision=qew.QEW_FP64_PLAIN)
+    meas = workloads.log_steps(n, pts)
+    v = []
+    for f in drives:
+        p = workloads.custom(0, [L] * 2, f, n, meas, SEED + 60, disorder_id=[0, 1])
+        v.append(oracle.run(p)["v"].mean(0))
+    assert rel_err(r["v"], np.array(v), floor=1e-3) <= 1e-10
+    f_lo, f_hi, signs = std.bracket_fc(drives, meas * 0.05, np.array(v))
+    assert (r["f_lo"], r["f_hi"]) == (f_lo, f_hi)
+    assert np.array_equal(r["signs"], signs)
