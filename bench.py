@@ -247,18 +247,17 @@ def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
 
 
 # Workloads besides the benchmark line: name -> (description, builder(steps)).
-# The drives of the L = 2^25 workloads sit at the critical force bracketed by
-# the f-scan of `paper_1211_7275_amd.std` (L = 2^16, 10^5 steps).
-FC_SCAN = {0: 1.00, 1: 1.00}
+# The drives of the L = 2^25 workloads sit around the critical force bracketed
+# by the f-scan of `paper_1211_7275_amd.std` (workloads.C4_FCENTER).
 OTHER_WORKLOADS = {
     "c1": ("L=2^16 RB Catmull-Rom Gaussian, 64 disorders x f in {0.8, 1.0, 1.2}",
            lambda n: workloads.config1(n_steps=n)),
     "c2": ("512 RF samples, L_s = 2^10..2^16 (uneven batch), f=1.0",
            lambda n: workloads.config2(n_steps=n)),
     "c4rf": ("L=2^25 x 5 drives around f_c, RF Catmull-Rom uniform, one disorder",
-             lambda n: workloads.config4(0, FC_SCAN[0], n_steps=n)),
+             lambda n: workloads.config4(0, n_steps=n)),
     "c4rb": ("L=2^25 x 5 drives around f_c, RB Catmull-Rom Gaussian, one disorder",
-             lambda n: workloads.config4(1, FC_SCAN[1], n_steps=n)),
+             lambda n: workloads.config4(1, n_steps=n)),
 }
 
 

@@ -175,7 +175,8 @@ def main(argv=None):
     out = {"kind": a.kind, "L": a.L, "steps": a.steps, "disorders": a.disorders,
            "coarse": describe(rc)}
     if rc["f_lo"] is not None and rc["f_hi"] is not None and rc["f_lo"] < rc["f_hi"]:
-        fine = np.round(np.arange(rc["f_lo"], rc["f_hi"] + a.f_step / 2, a.f_step), 10)
+        fine = np.round(np.arange(rc["f_lo"], rc["f_hi"], a.f_step), 10)
+        fine = np.append(fine[fine < rc["f_hi"] - 1e-9], rc["f_hi"])
         rf = fscan(a.kind, a.L, fine, a.steps, a.points, a.seed, disorders=a.disorders)
         out["fine"] = describe(rf)
         out["f_lo"], out["f_hi"] = rf["f_lo"], rf["f_hi"]

@@ -93,8 +93,17 @@ def config3(n_steps=1_000_000, n_meas=200, samples=4, L=1 << 22):
                     SEED_BASE + 3)
 
 
-def config4(kind, f_center, n_steps=1_000_000, n_meas=200, L=1 << 25, spacing=0.02):
-    """Paper scale: L=2^25, one disorder, 5 drives spaced 0.02 around f_center."""
+# Largest drive whose velocity still dies in the f-scan at L = 2^16 (4 disorders,
+# 10^5 steps, drives 0.02 apart, `python -m paper_1211_7275_amd.std`): the
+# threshold of the unit-strength disorder lies between this drive and the next.
+C4_FCENTER = {RF: 0.363, RB: 1.937}
+
+
+def config4(kind, f_center=None, n_steps=1_000_000, n_meas=200, L=1 << 25, spacing=0.02):
+    """Paper scale: L=2^25, one disorder, 5 drives spaced 0.02 around f_center
+    (default: the f-scan's last dying drive for this kind)."""
+    if f_center is None:
+        f_center = C4_FCENTER[kind]
     f = f_center + spacing * np.arange(-2, 3)
     return _problem(kind, [L] * 5, f, np.zeros(5, np.uint32), n_steps, n_meas,
                     SEED_BASE + 4 + int(kind))

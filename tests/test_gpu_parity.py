@@ -476,6 +476,41 @@ def test_full_size_l2e22_sampled_sites(qew, oracle):
     assert np.max(np.abs(d - 0.05 * out["v"][:, :-1])) <= 1e-6
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_full_size_l2e25_sampled_sites(qew, oracle, kind):
+    """L = 2^25 x 5 drives around the threshold, one shared disorder (the
+    paper-scale workload), fused with the autotuned geometry: sampled sites
+    against the oracle's light-cone windows, v(0) from the oracle's node means,
+    and d ubar = dt v at every step."""
+    N = 32
+    p = workloads.config4(kind, n_steps=N, n_meas=2)
+    p["meas_steps"] = np.arange(0, N + 1)
+    L = int(p["L"][0])
+    say("full size L=2^25 x 5, kind", kind, "fused, autotuned, 32 steps")
+    sim = qew.Simulation(p, precision=qew.QEW_FP32_SPLIT, path=qew.QEW_FUSED)
+    try:
+        out = sim.run()
+        info = sim.info()
+        say("  autotuned k", info.k, "tile", info.tile)
+        V = info.tile - 2 * info.k
+        rng = np.random.default_rng(4)
+        for s in (0, 4):
+            u, _ = sim.read_state(s)
+            picks = {0, 1, L - 1, V - 1, V, L // 2} | set(rng.integers(0, L, 8))
+            for jj in sorted(picks):
+                ref = oracle.site_after(kind, 1.0, p["seed"], 0, L, jj, 1.0, 0.05, p["f"][s], N)
+                assert abs(u[jj] - ref) <= 1e-4, (s, jj)
+    finally:
+        sim.close()
+    if kind == 0:
+        fp0 = oracle.mean_node(0, p["seed"], 0, L, 0)
+    else:  # RB: F_p(0) = -dCR/ds at s = 0 = -(R(1) - R(-1)) / 2
+        fp0 = -(oracle.mean_node(1, p["seed"], 0, L, 1) - oracle.mean_node(1, p["seed"], 0, L, -1)) / 2
+    assert np.max(np.abs(out["v"][:, 0] - (p["f"] + fp0))) <= 1e-6
+    d = np.diff(out["ubar"], axis=1)
+    assert np.max(np.abs(d - 0.05 * out["v"][:, :-1])) <= 1e-6
+
+
 def test_full_size_l2e22_fp64_plain_sampled_sites(qew, oracle):
     N = 12
     p = workloads.config3(n_steps=N, n_meas=2)
