@@ -36,6 +36,17 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Wave-wide lane shifts by one (DPP wave_shr:1 / wave_shl:1): lane l receives
+// x of lane l - 1 (resp. l + 1); lane 0 (resp. 63) keeps its own x.
+__device__ __forceinline__ float from_lower_lane(float x) {
+  const int v = __float_as_int(x);
+  return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_upper_lane(float x) {
+  const int v = __float_as_int(x);
+  return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -211,14 +222,13 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 constexpr int kReqPerWave = QEW_REQ_PER_WAVE;
 
 template <int KIND, int P>
-__global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
+__global__ void __launch_bounds__(kBlock, P == 6 ? 5 : (P <= 8 ? QEW_FUSED_MIN_WAVES : (P == 12 ? 3 : 2)))
     k_step_fused(Tables t, SplitBuf in, SplitBuf out, Phys ph, int halo, int nsub) {
   constexpr int T = kBlock * P;
   constexpr int NW = kBlock / 64;
   constexpr int RQ = kReqPerWave;
   __shared__ float4 s_nodes[T];
   __shared__ int4 s_req[NW * RQ];
-  __shared__ int s_count[2][NW];
   __shared__ float2 s_edge[2][NW][2];
 
   const int tid = threadIdx.x;
@@ -237,7 +247,8 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
     const int start = p0 - halo;
     int start_mod = start % L;
     if (start_mod < 0) start_mod += L;
-    const bool contiguous = start >= 0 && start + T <= L && (start & 3) == 0;
+    constexpr int VW = (P % 4 == 0) ? 4 : 2;  // sites per vector load / store
+    const bool contiguous = start >= 0 && start + T <= L && (start % VW) == 0;
     const int32_t cbase = uniform_i32(in.cell[base + start_mod]);
 
     float c[P];  // cell - cbase, an exact integer
@@ -247,16 +258,27 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
     if (contiguous) {
       const int64_t gi = base + start + tid * P;
 #pragma unroll
-      for (int v = 0; v < P / 4; ++v) {
-        const int4 cv = *reinterpret_cast<const int4*>(in.cell + gi + 4 * v);
-        const float4 rv = *reinterpret_cast<const float4*>(in.frac + gi + 4 * v);
-        const int32_t cc[4] = {cv.x - cbase, cv.y - cbase, cv.z - cbase, cv.w - cbase};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          far |= (uint32_t)(cc[e] + (1 << 23)) >= (1u << 24);
-          c[4 * v + e] = (float)cc[e];
+      for (int v = 0; v < P / VW; ++v) {
+        int32_t cc[VW];
+        float rr[VW];
+        if constexpr (VW == 4) {
+          const int4 cv = *reinterpret_cast<const int4*>(in.cell + gi + 4 * v);
+          const float4 rv = *reinterpret_cast<const float4*>(in.frac + gi + 4 * v);
+          cc[0] = cv.x; cc[1] = cv.y; cc[2] = cv.z; cc[3] = cv.w;
+          rr[0] = rv.x; rr[1] = rv.y; rr[2] = rv.z; rr[3] = rv.w;
+        } else {
+          const int2 cv = *reinterpret_cast<const int2*>(in.cell + gi + 2 * v);
+          const float2 rv = *reinterpret_cast<const float2*>(in.frac + gi + 2 * v);
+          cc[0] = cv.x; cc[1] = cv.y;
+          rr[0] = rv.x; rr[1] = rv.y;
         }
-        r[4 * v] = rv.x; r[4 * v + 1] = rv.y; r[4 * v + 2] = rv.z; r[4 * v + 3] = rv.w;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const int32_t d = cc[e] - cbase;
+          far |= (uint32_t)(d + (1 << 23)) >= (1u << 24);
+          c[VW * v + e] = (float)d;
+          r[VW * v + e] = rr[e];
+        }
       }
 #pragma unroll
       for (int i = 0; i < P; ++i) {
@@ -286,10 +308,10 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
     for (int sub = 0; sub < nsub; ++sub) {
       const int par = sub & 1;
       // Neighbours of this thread's end sites.  The tile ends reflect.
-      float cle = __shfl_up(c[P - 1], 1, 64);
-      float rle = __shfl_up(r[P - 1], 1, 64);
-      float cre = __shfl_down(c[0], 1, 64);
-      float rre = __shfl_down(r[0], 1, 64);
+      float cle = from_lower_lane(c[P - 1]);
+      float rle = from_lower_lane(r[P - 1]);
+      float cre = from_upper_lane(c[0]);
+      float rre = from_upper_lane(r[0]);
       if (lane == 0) {
         if (wv > 0) {
           const float2 e = s_edge[par][wv - 1][1];
@@ -321,8 +343,11 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
       for (int v = 0; v < (P + 3) / 4; ++v) rk[v] = 0u;
       uint32_t pending = 0u;
       uint32_t nreq = 0u;  // wave-uniform
+      float oc[P];          // cells before the step
       float dl = c[0] - cle;  // cell difference to the left neighbour
       float pr = rle;
+      // All steps first (independent chains the scheduler can interleave),
+      // then the requests of the sites that changed cell.
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const float nc = (i + 1 < P) ? c[i + 1] : cre;
@@ -332,14 +357,17 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
         const float F = fmaf(cel, lap, spline_eval<KIND>(a[i], r[i]));
         dl = dr;
         pr = r[i];
-        const float oc = c[i];
-        const float fl = split_advance(r[i], F, dt);
-        c[i] = oc + fl;
-        const uint64_t moved = __ballot(fl != 0.0f);
-        if (fl != 0.0f) {
+        oc[i] = c[i];
+        c[i] = oc[i] + split_advance(r[i], F, dt);
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const bool mv = c[i] != oc[i];
+        const uint64_t moved = __ballot(mv);
+        if (mv) {
           const uint32_t k = nreq + mbcnt64(moved);
           if (k < (uint32_t)RQ) {
-            s_req[wv * RQ + k] = make_int4(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc), 0);
+            s_req[wv * RQ + k] = make_int4(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc[i]), 0);
             rk[i / 4] |= (k + 1u) << (8 * (i % 4));
           } else {
             pending |= 1u << i;
@@ -347,24 +375,15 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
         }
         nreq += (uint32_t)__popcll(moved);
       }
-      if (lane == 0) {
-        s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
-        s_count[par][wv] = (int)(nreq < (uint32_t)RQ ? nreq : (uint32_t)RQ);
-      }
-      if (lane == 63) s_edge[par ^ 1][wv][1] = make_float2(c[P - 1], r[P - 1]);
-      __syncthreads();
-
-      int pre[NW + 1];
-      pre[0] = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) pre[w + 1] = pre[w] + uniform_i32(s_count[par][w]);
-      if (pre[NW] > 0) {
-        // Serve the posted requests with the whole workgroup.
-        for (int q = tid; q < pre[NW]; q += kBlock) {
-          int w = 0;
-#pragma unroll
-          for (int x = 1; x < NW; ++x) w += (q >= pre[x]) ? 1 : 0;
-          const int slot = w * RQ + (q - pre[w]);
+      // Serve this wave's requests with this wave's lanes: lane q takes request
+      // q.  The requests, their node windows and the replies belong to this
+      // wave only, and a wave's LDS operations complete in program order, so
+      // no workgroup barrier is needed between posting, serving and reading.
+      const uint32_t nserve = nreq < (uint32_t)RQ ? nreq : (uint32_t)RQ;
+      if (nserve > 0u) {
+        __builtin_amdgcn_wave_barrier();
+        if ((uint32_t)lane < nserve) {
+          const int slot = wv * RQ + lane;
           const int4 rq = s_req[slot];  // {node index, new cell, old cell} (cells relative to cbase)
           const int ni = rq.x;
           const float cnew = __int_as_float(rq.y);
@@ -390,7 +409,8 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
           s_req[slot] = make_int4(__float_as_int(co.x), __float_as_int(co.y), __float_as_int(co.z),
                                   __float_as_int(co.w));
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         // Requesters read their new coefficients.
 #pragma unroll
         for (int i = 0; i < P; ++i) {
@@ -401,6 +421,7 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
                                __int_as_float(v.w));
           }
         }
+        __builtin_amdgcn_wave_barrier();
       }
       // Rare: requests beyond the region (a burst of cell changes) are served
       // by their own lane: regenerate the window of the new cell.
@@ -408,7 +429,9 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
 #pragma unroll
         for (int i = 0; i < P; ++i) {
           if ((pending >> i) & 1u) {
-            int j = start_mod + tid * P + i;
+            int j = start_mod + tid * P;
+            asm volatile("" : "+v"(j));  // keep this rare path's index arithmetic here
+            j += i;
             if (j >= L) j -= L;
             if (j >= L) j %= L;
             const int32_t cell = cbase + (int32_t)c[i];
@@ -421,20 +444,30 @@ __global__ void __launch_bounds__(kBlock, P <= 8 ? QEW_FUSED_MIN_WAVES : 2)
           }
         }
       }
+      // Publish this wave's end sites for the neighbouring waves' next sub-step.
+      if (lane == 0) s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
+      if (lane == 63) s_edge[par ^ 1][wv][1] = make_float2(c[P - 1], r[P - 1]);
+      __syncthreads();
     }
 
     // Write the valid part: tile-local q in [halo, halo + len).
     int qb = tid * P;
     asm volatile("" : "+v"(qb));
     const int64_t g0 = base + p0 + (qb - halo);
-    if (qb >= halo && qb + P <= halo + len && (g0 & 3) == 0) {
+    if (qb >= halo && qb + P <= halo + len && (g0 % VW) == 0) {
 #pragma unroll
-      for (int v = 0; v < P / 4; ++v) {
-        *reinterpret_cast<int4*>(out.cell + g0 + 4 * v) =
-            make_int4(cbase + (int32_t)c[4 * v], cbase + (int32_t)c[4 * v + 1],
-                      cbase + (int32_t)c[4 * v + 2], cbase + (int32_t)c[4 * v + 3]);
-        *reinterpret_cast<float4*>(out.frac + g0 + 4 * v) =
-            make_float4(r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+      for (int v = 0; v < P / VW; ++v) {
+        if constexpr (VW == 4) {
+          *reinterpret_cast<int4*>(out.cell + g0 + 4 * v) =
+              make_int4(cbase + (int32_t)c[4 * v], cbase + (int32_t)c[4 * v + 1],
+                        cbase + (int32_t)c[4 * v + 2], cbase + (int32_t)c[4 * v + 3]);
+          *reinterpret_cast<float4*>(out.frac + g0 + 4 * v) =
+              make_float4(r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+        } else {
+          *reinterpret_cast<int2*>(out.cell + g0 + 2 * v) =
+              make_int2(cbase + (int32_t)c[2 * v], cbase + (int32_t)c[2 * v + 1]);
+          *reinterpret_cast<float2*>(out.frac + g0 + 2 * v) = make_float2(r[2 * v], r[2 * v + 1]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < P; ++i) out.nodes[g0 + i] = s_nodes[i * kBlock + tid];
@@ -711,11 +744,21 @@ static const void* fused_ptr() {
   return reinterpret_cast<const void*>(&k_step_fused<KIND, P>);
 }
 
+static const void* fused_fn(int tile) {
+  switch (tile) {
+    case 1024: return fused_ptr<kRF, 4>();
+    case 1536: return fused_ptr<kRF, 6>();
+    case 2048: return fused_ptr<kRF, 8>();
+    case 3072: return fused_ptr<kRF, 12>();
+    default: return fused_ptr<kRF, 16>();
+  }
+}
+
 int fused_max_grid(int tile) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* fn = tile == 1024 ? fused_ptr<kRF, 4>() : tile == 2048 ? fused_ptr<kRF, 8>() : fused_ptr<kRF, 16>();
+  const void* fn = fused_fn(tile);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess) return 0;
   if (per_cu < 1) per_cu = 1;
   return cus * per_cu;
@@ -727,7 +770,7 @@ bool fused_fits(int tile) {
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return false;
   hipFuncAttributes attr{};
-  const void* fn = tile == 1024 ? fused_ptr<kRF, 4>() : tile == 2048 ? fused_ptr<kRF, 8>() : fused_ptr<kRF, 16>();
+  const void* fn = fused_fn(tile);
   if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return false;
   return (int)attr.sharedSizeBytes <= max_lds;
 }
@@ -736,7 +779,9 @@ template <int KIND>
 static void launch_fused_kind(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int tile,
                               int halo, int nsub, dim3 g, dim3 b, hipStream_t st) {
   if (tile == 1024) hipLaunchKernelGGL((k_step_fused<KIND, 4>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else if (tile == 1536) hipLaunchKernelGGL((k_step_fused<KIND, 6>), g, b, 0, st, t, in, out, ph, halo, nsub);
   else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<KIND, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else if (tile == 3072) hipLaunchKernelGGL((k_step_fused<KIND, 12>), g, b, 0, st, t, in, out, ph, halo, nsub);
   else hipLaunchKernelGGL((k_step_fused<KIND, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
 }
 

@@ -46,7 +46,7 @@ qew_status fail(qew_status st, const char* fmt, ...) {
 
 constexpr int64_t kMaxL = int64_t(1) << 30;
 constexpr int kGraphLaunches = 16;
-constexpr int kTuneTiles[3] = {1024, 2048, 4096};
+constexpr int kTuneTiles[5] = {1024, 1536, 2048, 3072, 4096};
 constexpr int kTuneK[3] = {8, 16, 32};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -459,8 +459,9 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
   if (pr->path == QEW_FUSED && pr->precision != QEW_FP32_SPLIT)
     return fail(QEW_EUNSUPPORTED, "the fused path runs in FP32 split precision only");
   if (pr->k < 0 || pr->k > kMaxHalo) return fail(QEW_EINVAL, "k must be in [0, %d]", kMaxHalo);
-  if (pr->tile != 0 && pr->tile != 1024 && pr->tile != 2048 && pr->tile != 4096)
-    return fail(QEW_EINVAL, "tile must be 0, 1024, 2048 or 4096");
+  if (pr->tile != 0 && pr->tile != 1024 && pr->tile != 1536 && pr->tile != 2048 && pr->tile != 3072 &&
+      pr->tile != 4096)
+    return fail(QEW_EINVAL, "tile must be 0, 1024, 1536, 2048, 3072 or 4096");
   if (pr->k > 0 && pr->tile > 0 && 4 * pr->k > pr->tile) return fail(QEW_EINVAL, "need 4*k <= tile");
   if (pr->flags & ~(QEW_FLAG_NO_GRAPH | QEW_FLAG_TIMING)) return fail(QEW_EINVAL, "unknown flag bits");
   if (pr->sq_bins < 0) return fail(QEW_EINVAL, "sq_bins must be >= 0");

@@ -178,7 +178,7 @@ def test_ensemble_on_device(qew, c0_oracle):
 
 # -------------------------------------------- fused == one-step (bitwise) --
 
-GEOMS = [(1, 1024), (5, 1024), (8, 1024), (16, 2048), (32, 2048), (32, 4096), (64, 4096)]
+GEOMS = [(1, 1024), (5, 1024), (8, 1024), (13, 1536), (32, 1536), (16, 2048), (32, 2048), (32, 4096), (64, 4096)]
 SIZES = [3, 5, 31, 64, 100, 511, 1000, 1024, 1500, 5000]
 
 
