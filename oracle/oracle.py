@@ -58,6 +58,9 @@ def lib():
     L.qo_run_window.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_i64, c_i64, c_i64, c_d, c_d,
                                 c_d, c_i64, f64p]
     L.qo_run_window.restype = c_int
+    L.qo_relax.argtypes = [c_int, c_d, c_u64, c_u32, c_i64, c_i64, c_d, c_d, c_d, f64p, f64p,
+                           c_i64, c_d, ctypes.POINTER(c_i64)]
+    L.qo_relax.restype = c_int
     L.qo_mean_node.argtypes = [c_int, c_u64, c_u32, c_i64, c_i64]
     L.qo_mean_node.restype = c_d
     L.qo_set_threads.argtypes = [c_int]
@@ -241,3 +244,52 @@ def sq_series(problem, edges):
         for i, u in enumerate(states_at(problem, s, meas)):
             acc[i] += sq_binned(structure_factor(u), edges)
     return acc / S
+
+
+# --------------------------------------------------------------------------
+# Critical force and configuration of a sample periodic in u (Sec. III A): the
+# pinned solution of c d2u/dx2 + F_p + f = 0 with the largest f, by bisection
+# on f.  Each trial relaxes from the last pinned configuration found (below
+# the critical one, where the line moves forward only), and the trial decides
+# pinned (all forces below tol) or depinned (the line advanced by a full
+# period M, impossible while a pinned configuration exists).
+# --------------------------------------------------------------------------
+
+PINNED, DEPINNED, UNDECIDED = 0, 1, 2
+
+
+def relax(kind, strength, seed, did, M, c, dt, f, u, u_ref, max_steps, tol):
+    """One relaxation (see qo_relax); returns (status, steps) and updates u in place."""
+    steps = ctypes.c_int64()
+    rc = lib().qo_relax(int(kind), float(strength), int(seed), int(did), int(M), u.size,
+                        float(c), float(dt), float(f), u, np.ascontiguousarray(u_ref, np.float64),
+                        int(max_steps), float(tol), ctypes.byref(steps))
+    if rc < 0:
+        raise ValueError("oracle qo_relax rejected its input")
+    return rc, int(steps.value)
+
+
+def critical_force(kind, strength, seed, did, L, M, c=1.0, dt=0.05, f_lo=0.0, f_hi=5.0,
+                   tol_f=1e-6, tol_force=1e-10, max_steps=10_000_000):
+    """Bisection for f_c^s of one sample.  Returns dict(f_lo, f_hi, u_c, trials)
+    with f_c^s in [f_lo, f_hi), f_hi - f_lo < tol_f, u_c the pinned
+    configuration at f_lo and trials the (f, status, steps) of every relaxation."""
+    u = np.zeros(int(L), np.float64)
+    trials = []
+    st, n = relax(kind, strength, seed, did, M, c, dt, f_lo, u, np.full(u.size, np.inf), max_steps,
+                  tol_force)
+    trials.append((f_lo, st, n))
+    if st != PINNED:
+        raise ValueError("no pinned configuration at the lower drive")
+    while f_hi - f_lo >= tol_f:
+        f_mid = 0.5 * (f_lo + f_hi)
+        v = u.copy()
+        st, n = relax(kind, strength, seed, did, M, c, dt, f_mid, v, u, max_steps, tol_force)
+        trials.append((f_mid, st, n))
+        if st == PINNED:
+            f_lo, u = f_mid, v
+        elif st == DEPINNED:
+            f_hi = f_mid
+        else:
+            raise ValueError("relaxation undecided within max_steps")
+    return {"f_lo": f_lo, "f_hi": f_hi, "u_c": u, "trials": trials}

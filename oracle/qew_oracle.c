@@ -354,3 +354,46 @@ int qo_get_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Critical configuration of a sample periodic in u (period M > 0), Sec. III A
+ * (its definition: the pinned solution of c d2u/dx2 + F_p(u, x) + f = 0 with
+ * the largest f).  One relaxation: Euler steps of Eq. (1) at drive f from u
+ * (in place) until
+ *   - every |F_j| <= tol: a pinned configuration (returns 0);
+ *   - min_j (u_j - u_ref_j) >= M: the line has advanced by a full period of
+ *     the medium, which it cannot do if a pinned configuration exists at this
+ *     f (started below one, a forward-moving line never passes it, and its
+ *     translates by M are pinned too), so f is above the critical force
+ *     (returns 1);
+ *   - max_steps steps were taken (returns 2: undecided).
+ * *steps receives the number of steps taken.  Returns -1 on bad input.
+ */
+int qo_relax(int kind, double strength, uint64_t seed, uint32_t disorder_id, int64_t period,
+             int64_t L, double c, double dt, double f, double *u, const double *u_ref,
+             int64_t max_steps, double tol, int64_t *steps)
+{
+    if (L < 1 || period < 1 || max_steps < 0 || !(tol > 0)) return -1;
+    double *F = (double *)malloc((size_t)L * sizeof(double));
+    double *un = (double *)malloc((size_t)L * sizeof(double));
+    if (!F || !un) { free(F); free(un); return -1; }
+    int rc = 2;
+    int64_t m = 0;
+    for (;; ++m) {
+        qo_forces(kind, strength, seed, disorder_id, period, L, c, f, u, F);
+        double fmax = 0.0, adv = INFINITY;
+        for (int64_t j = 0; j < L; ++j) {
+            if (fabs(F[j]) > fmax) fmax = fabs(F[j]);
+            if (u[j] - u_ref[j] < adv) adv = u[j] - u_ref[j];
+        }
+        if (fmax <= tol) { rc = 0; break; }
+        if (adv >= (double)period) { rc = 1; break; }
+        if (m == max_steps) break;
+        qo_euler(L, dt, u, F, un);
+        memcpy(u, un, (size_t)L * sizeof(double));
+    }
+    *steps = m;
+    free(F);
+    free(un);
+    return rc;
+}

@@ -507,3 +507,58 @@ def test_states_at_equals_uninterrupted_runs(oracle):
     for m, u in zip([0, 1, 7, 50], got):
         ref = oracle.run_sample(0, 1.0, p["seed"], 0, 96, 1.0, 0.05, 1.1, m, [])["u"]
         assert np.array_equal(u, ref)
+
+
+# ----------------------------------- critical force of a periodic sample (Sec. III A)
+
+def test_critical_force_without_disorder_is_zero(oracle):
+    """No pinning force: the flat line is pinned at f = 0 only, any f > 0 moves it."""
+    r = oracle.critical_force(oracle.RF, 0.0, SEED, 0, 32, 2, f_hi=1.0, tol_f=2e-3)
+    assert r["f_lo"] == 0.0 and r["f_hi"] < 2e-3
+    assert np.all(r["u_c"] == 0.0)
+
+
+def test_pinned_configurations_are_ordered(oracle):
+    """No-passing (Middleton): pinned configurations reached from below at
+    f1 < f2 are ordered site by site, and each solves c d2u + F_p + f = 0."""
+    L, M = 64, 32
+    u1 = np.zeros(L)
+    st, _ = oracle.relax(oracle.RB, 1.0, SEED, 2, M, 1.0, 0.05, 0.5, u1, np.full(L, np.inf),
+                         10**7, 1e-11)
+    assert st == oracle.PINNED
+    u2 = u1.copy()
+    st, _ = oracle.relax(oracle.RB, 1.0, SEED, 2, M, 1.0, 0.05, 1.2, u2, u1, 10**7, 1e-11)
+    assert st == oracle.PINNED
+    assert np.all(u2 >= u1)
+    F = oracle.forces(oracle.RB, 1.0, SEED, 2, 1.0, 1.2, u2, period=M)
+    assert np.max(np.abs(F)) <= 1e-11
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_critical_configuration_is_a_saddle_node(oracle, kind):
+    """At f_c^s the pinned solution disappears in a saddle-node bifurcation:
+    the smallest eigenvalue of the stiffness matrix -dF/du (periodic
+    tridiagonal c Laplacian plus the local slope of F_p) vanishes like
+    sqrt(f_c - f).  It is positive (stable) at the configuration the bisection
+    returns and much smaller there than at half the critical force."""
+    L, M, c = 48, 48, 1.0
+    r = oracle.critical_force(kind, 1.0, SEED, 1, L, M, f_hi=4.0, tol_f=1e-7, tol_force=1e-11)
+
+    def lam_min(u):
+        h = 1e-6
+        slope = np.array([(oracle.pinning(kind, 1.0, SEED, 1, j, u[j] + h, M)
+                           - oracle.pinning(kind, 1.0, SEED, 1, j, u[j] - h, M)) / (2 * h)
+                          for j in range(L)])
+        K = np.diag(2 * c - slope) - c * (np.eye(L, k=1) + np.eye(L, k=-1))
+        K[0, -1] = K[-1, 0] = -c
+        return np.linalg.eigvalsh(K)[0]
+
+    lam_c = lam_min(r["u_c"])
+    u_half = np.zeros(L)
+    st, _ = oracle.relax(kind, 1.0, SEED, 1, M, c, 0.05, 0.5 * r["f_lo"], u_half,
+                         np.full(L, np.inf), 10**7, 1e-11)
+    assert st == oracle.PINNED
+    lam_half = lam_min(u_half)
+    assert 0 < lam_c < 0.1 * lam_half
+    # sqrt scaling: at distance < 1e-7 below f_c the eigenvalue is O(1e-3)
+    assert lam_c < 0.02
