@@ -645,3 +645,23 @@ def test_fscan_gpu_matches_oracle(qew, oracle):
     f_lo, f_hi, signs = std.bracket_fc(drives, meas * 0.05, np.array(v))
     assert (r["f_lo"], r["f_hi"]) == (f_lo, f_hi)
     assert np.array_equal(r["signs"], signs)
+
+
+# ----------------------------- critical force of periodic samples (Sec. III A)
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_critical_forces_match_oracle(qew, oracle, kind):
+    """Batched bisection through the library (FP64) against the oracle's
+    bisection of the same samples: the same bracket of f_c^s and the same
+    critical configuration per site."""
+    from paper_1211_7275_amd import critical
+    L, M, tol_f = 64, 64, 1e-4
+    dids = [0, 1, 2]
+    say("critical forces kind", kind)
+    r = critical.critical_forces(kind, L, M, dids, SEED + 70, f_hi=4.0, tol_f=tol_f)
+    for s, d in enumerate(dids):
+        ref = oracle.critical_force(kind, 1.0, SEED + 70, d, L, M, f_hi=4.0, tol_f=tol_f)
+        say("  sample", d, "gpu", r["f_lo"][s], "oracle", ref["f_lo"])
+        assert abs(r["f_lo"][s] - ref["f_lo"]) <= tol_f
+        if r["f_lo"][s] == ref["f_lo"]:
+            assert np.max(np.abs(r["u_c"][s] - ref["u_c"])) <= 1e-6
