@@ -47,7 +47,7 @@ qew_status fail(qew_status st, const char* fmt, ...) {
 constexpr int64_t kMaxL = int64_t(1) << 30;
 constexpr int kGraphLaunches = 16;
 constexpr int kTuneTiles[5] = {1024, 1536, 2048, 3072, 4096};
-constexpr int kTuneK[3] = {8, 16, 32};
+constexpr int kTuneK[4] = {16, 32, 48, 64};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
