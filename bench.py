@@ -258,6 +258,14 @@ OTHER_WORKLOADS = {
              lambda n: workloads.config4(0, n_steps=n)),
     "c4rb": ("L=2^25 x 5 drives around f_c, RB Catmull-Rom Gaussian, one disorder",
              lambda n: workloads.config4(1, n_steps=n)),
+    "c3ref": ("the benchmark workload (L=2^22 x 4 RF) timed on this horizon like the other "
+              "workloads (reference for c3sq)", lambda n: bench_problem(n)),
+    "c3sq": ("the benchmark workload (L=2^22 x 4 RF) with the structure factor in 64 log-spaced "
+             "mode bins at every measurement",
+             lambda n: dict(bench_problem(n), sq_edges=workloads.sq_edges_log(1 << 22, 64))),
+    "sq8192": ("structure factor at the shape of Fig. 4: L=8192 x 64 RF samples, every mode, "
+               "30 log-spaced measurements",
+               lambda n: workloads.config_sq(n_steps=n)),
 }
 
 
@@ -278,6 +286,7 @@ def other_workload(qew, args):
                        "total_sites": int(info.total_sites),
                        "measurements": int(len(p["meas_steps"])), "k": info.k, "tile": info.tile},
             "roofline": roof,
+            "meas_ms_per_measurement": round(st.meas_ms / max(st.meas_launches, 1), 4),
             "v_last_mean": float(np.nanmean(out["v"][:, -1])) if out["v"].shape[1] else None}
 
 
