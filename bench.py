@@ -191,7 +191,7 @@ def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
         return out
 
     def short(n):
-        return n.split("(")[0].replace("void ", "")
+        return n.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
 
     lines = []
     stats = rows("*kernel_stats.csv")

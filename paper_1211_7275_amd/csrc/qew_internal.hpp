@@ -81,8 +81,12 @@ hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1
 // Structure factor at one measurement: pack, FFT passes, per-mode |U_n/L|^2,
 // binned mean over samples into out[n_bins].  Every L_s equals L (power of
 // two); u_plain != nullptr selects the FP64 state, else `split`.
+// The bins are cut into n_chunks chunks of modes [chunk_lo[c], chunk_lo[c+1])
+// (bin b owns chunks chunk_first[b] .. chunk_first[b+1]-1); `part` holds one
+// partial sum per chunk.
 hipError_t launch_sq(const int64_t* off, int S, int64_t L, const double* u_plain, SplitBuf split,
-                     double2* bufA, double2* bufB, const int64_t* edges, int n_bins, double* out,
+                     double2* bufA, double2* bufB, const int32_t* chunk_lo, int n_chunks,
+                     const int32_t* chunk_first, int n_bins, double* part, double* out,
                      hipStream_t st);
 
 }  // namespace qew

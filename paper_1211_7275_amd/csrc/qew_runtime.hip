@@ -46,15 +46,17 @@ qew_status fail(qew_status st, const char* fmt, ...) {
 
 constexpr int64_t kMaxL = int64_t(1) << 30;
 constexpr int kGraphLaunches = 16;
+constexpr int64_t kSqChunk = 4096;  // modes per binning chunk
 constexpr int kTuneTiles[5] = {1024, 1536, 2048, 3072, 4096};
 constexpr int kTuneK[4] = {16, 32, 48, 64};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t err, off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len, sq_edges;
+  size_t err, off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len, sq_chunk_lo,
+      sq_chunk_first;
   size_t tables_end;
-  size_t part, series, ens, sq_series, fftA, fftB, stA0, stA1, stB0, stB1, ndA, ndB;
+  size_t part, series, ens, sq_series, sq_part, fftA, fftB, stA0, stA1, stB0, stB1, ndA, ndB;
   size_t total;
 };
 
@@ -71,6 +73,8 @@ struct qew_plan_s {
   int32_t S = 0, kind = 0, precision = 0, path = 0, k_req = 0, tile_req = 0, flags = 0, period = 0;
   int32_t sq_bins = 0;
   std::vector<int64_t> sq_edges;
+  std::vector<int32_t> sq_chunk_lo;     // [n_chunks + 1] mode ranges of the binning chunks
+  std::vector<int32_t> sq_chunk_first;  // [sq_bins + 1] first chunk of each bin
   double c = 0, dt = 0, strength = 0;
   uint64_t seed = 0;
   int64_t n_steps = 0;
@@ -148,7 +152,8 @@ void compute_layout(qew_plan_t* p) {
   l.ft_s = take(nft * 4);
   l.ft_p0 = take(nft * 4);
   l.ft_len = take(nft * 4);
-  l.sq_edges = take(p->sq_edges.size() * 8);
+  l.sq_chunk_lo = take(p->sq_chunk_lo.size() * 4);
+  l.sq_chunk_first = take(p->sq_chunk_first.size() * 4);
   l.tables_end = o;
   l.part = take(nmt * sizeof(Partial));
   l.series = take(S * std::max<size_t>(p->meas.size(), 1) * 3 * 8);
@@ -156,10 +161,11 @@ void compute_layout(qew_plan_t* p) {
   if (p->sq_bins > 0) {
     const size_t half = (size_t)(p->L[0] / 2);
     l.sq_series = take(std::max<size_t>(p->meas.size(), 1) * p->sq_bins * 8);
-    l.fftA = take(S * half * 16);
-    l.fftB = take(S * half * 16);
+    l.sq_part = take(p->sq_chunk_lo.size() * 8);
+    l.fftA = take(S * half * 16 + (half + 1) * 8);  // either buffer may hold S_n and the mean
+    l.fftB = take(S * half * 16 + (half + 1) * 8);  // also holds the per-mode mean
   } else {
-    l.sq_series = l.fftA = l.fftB = 0;
+    l.sq_series = l.sq_part = l.fftA = l.fftB = 0;
   }
   const size_t n = (size_t)p->padded;
   if (p->precision == QEW_FP64_PLAIN) {
@@ -258,7 +264,8 @@ std::vector<char> table_image(const qew_plan_t* p) {
   put(l.ft_s, p->ft_s.data(), p->ft_s.size() * 4);
   put(l.ft_p0, p->ft_p0.data(), p->ft_p0.size() * 4);
   put(l.ft_len, p->ft_len.data(), p->ft_len.size() * 4);
-  put(l.sq_edges, p->sq_edges.data(), p->sq_edges.size() * 8);
+  put(l.sq_chunk_lo, p->sq_chunk_lo.data(), p->sq_chunk_lo.size() * 4);
+  put(l.sq_chunk_first, p->sq_chunk_first.data(), p->sq_chunk_first.size() * 4);
   return img;
 }
 
@@ -407,7 +414,9 @@ qew_status measure(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
     QEW_HIP(launch_sq(t.off, p->S, p->L[0], plain ? plain_buf(p, ws, p->cur_buf) : nullptr,
                       plain ? SplitBuf{} : split_buf(p, ws, p->cur_buf),
                       reinterpret_cast<double2*>(b + p->lay.fftA), reinterpret_cast<double2*>(b + p->lay.fftB),
-                      reinterpret_cast<const int64_t*>(b + p->lay.sq_edges), p->sq_bins,
+                      reinterpret_cast<const int32_t*>(b + p->lay.sq_chunk_lo),
+                      (int)p->sq_chunk_lo.size() - 1, reinterpret_cast<const int32_t*>(b + p->lay.sq_chunk_first),
+                      p->sq_bins, reinterpret_cast<double*>(b + p->lay.sq_part),
                       reinterpret_cast<double*>(b + p->lay.sq_series) + (size_t)mi * p->sq_bins, st));
   }
   p->stats.meas_launches++;
@@ -493,7 +502,18 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
   p->flags = pr->flags;
   p->period = pr->period;
   p->sq_bins = pr->sq_bins;
-  if (pr->sq_bins > 0) p->sq_edges.assign(pr->sq_edges, pr->sq_edges + pr->sq_bins + 1);
+  if (pr->sq_bins > 0) {
+    p->sq_edges.assign(pr->sq_edges, pr->sq_edges + pr->sq_bins + 1);
+    // Each bin is cut into chunks of at most kSqChunk modes, summed by one
+    // workgroup each; a bin then adds its chunks' sums in order.
+    for (int32_t b = 0; b < p->sq_bins; ++b) {
+      p->sq_chunk_first.push_back((int32_t)p->sq_chunk_lo.size());
+      for (int64_t lo = p->sq_edges[b]; lo < p->sq_edges[b + 1]; lo += kSqChunk)
+        p->sq_chunk_lo.push_back((int32_t)lo);
+    }
+    p->sq_chunk_first.push_back((int32_t)p->sq_chunk_lo.size());
+    p->sq_chunk_lo.push_back((int32_t)p->sq_edges[p->sq_bins]);
+  }
   p->c = pr->c;
   p->dt = pr->dt;
   p->strength = pr->strength;

@@ -10,8 +10,9 @@
 // even and odd halves.  The complex transform is a Stockham auto-sort FFT in
 // passes of radix 8 (then 4 or 2): every pass reads and writes the batch once,
 // coalesced, with twiddles from sincospi in FP64.  The per-mode values are then
-// averaged over the samples and over caller-given ranges of n, in a fixed
-// order (no atomics), so repeated runs give identical bits.
+// averaged over the samples and over caller-given ranges of n (cut into
+// chunks of modes), in a fixed order (no atomics), so repeated runs give
+// identical bits.
 #include "qew_internal.hpp"
 
 namespace qew {
@@ -67,148 +68,188 @@ __device__ __forceinline__ void dft<8>(double2* v) {
   v[7] = csub(e[3], t3);
 }
 
+// All transform lengths are powers of two, so every index split below is a
+// shift or a mask.  blockIdx.y walks the samples (grid-stride for large S).
+
 // z[s][k] = (u_2k - K) + i (u_2k+1 - K), K = u_0 of sample s.
 __global__ void __launch_bounds__(kBlock)
     k_sq_pack_plain(const int64_t* __restrict__ off, const double* __restrict__ u, double2* __restrict__ z,
-                    int64_t N, int64_t total) {
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-    const int64_t s = i / N, k = i - s * N;
+                    int N, int S) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= N) return;
+  for (int s = blockIdx.y; s < S; s += gridDim.y) {
     const double* us = u + off[s];
     const double K = us[0];
-    z[i] = make_double2(us[2 * k] - K, us[2 * k + 1] - K);
+    z[(int64_t)s * N + k] = make_double2(us[2 * k] - K, us[2 * k + 1] - K);
   }
 }
 
 __global__ void __launch_bounds__(kBlock)
     k_sq_pack_split(const int64_t* __restrict__ off, const int32_t* __restrict__ cell,
-                    const float* __restrict__ frac, double2* __restrict__ z, int64_t N, int64_t total) {
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-    const int64_t s = i / N, k = i - s * N;
+                    const float* __restrict__ frac, double2* __restrict__ z, int N, int S) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= N) return;
+  for (int s = blockIdx.y; s < S; s += gridDim.y) {
     const int64_t b = off[s];
     const double K = (double)cell[b] + (double)frac[b];
     const double a0 = (double)cell[b + 2 * k] + (double)frac[b + 2 * k];
     const double a1 = (double)cell[b + 2 * k + 1] + (double)frac[b + 2 * k + 1];
-    z[i] = make_double2(a0 - K, a1 - K);
+    z[(int64_t)s * N + k] = make_double2(a0 - K, a1 - K);
   }
 }
 
-// One Stockham pass of radix R over every transform of the batch: Ns points of
-// each sub-transform are done, this pass makes them Ns * R.
+// One Stockham pass of radix R = 2^lgR over every transform of the batch:
+// sub-transforms of Ns = 2^lgNs points are done, this pass makes them Ns * R.
+// The twiddles exp(-2 pi i r k / (Ns R)) are powers of the r = 1 twiddle.
 template <int R>
 __global__ void __launch_bounds__(kBlock)
-    k_fft_pass(const double2* __restrict__ in, double2* __restrict__ out, int64_t N, int64_t Ns,
-               int64_t total) {
-  const int64_t NR = N / R;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-    const int64_t s = i / NR, j = i - s * NR;
-    const double2* a = in + s * N;
-    double2* o = out + s * N;
-    const int64_t k = j % Ns;
+    k_fft_pass(const double2* __restrict__ in, double2* __restrict__ out, int lgN, int lgNs, int S) {
+  constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
+  const int NR = 1 << (lgN - lgR);
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= NR) return;
+  const int k = j & ((1 << lgNs) - 1);
+  const int base = ((j >> lgNs) << (lgNs + lgR)) + k;
+  double2 w1 = make_double2(1.0, 0.0);
+  if (lgNs > 0) {
+    double sn, cs;
+    sincospi(-2.0 * (double)k / (double)(1 << (lgNs + lgR)), &sn, &cs);
+    w1 = make_double2(cs, sn);
+  }
+  for (int s = blockIdx.y; s < S; s += gridDim.y) {
+    const double2* a = in + ((int64_t)s << lgN);
+    double2* o = out + ((int64_t)s << lgN);
     double2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = a[j + r * NR];
-    if (Ns > 1) {
+    if (lgNs > 0) {
+      double2 w = w1;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        double sn, cs;
-        sincospi(-2.0 * (double)(r * k) / (double)(Ns * R), &sn, &cs);
-        v[r] = cmul(v[r], make_double2(cs, sn));
+        v[r] = cmul(v[r], w);
+        w = cmul(w, w1);
       }
     }
     dft<R>(v);
-    const int64_t base = (j / Ns) * Ns * R + k;
 #pragma unroll
-    for (int q = 0; q < R; ++q) o[base + q * Ns] = v[q];
+    for (int q = 0; q < R; ++q) o[base + (q << lgNs)] = v[q];
   }
 }
 
 // Real transform from the half-length complex one, and S_n = |U_n / L|^2 for
 // n = 0 .. N (sq[s][n], row length N + 1).
 __global__ void __launch_bounds__(kBlock)
-    k_sq_post(const double2* __restrict__ Z, double* __restrict__ sq, int64_t N, int64_t total,
-              double inv_l2) {
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-    const int64_t s = i / (N + 1), n = i - s * (N + 1);
-    const double2* zs = Z + s * N;
+    k_sq_post(const double2* __restrict__ Z, double* __restrict__ sq, int N, int S, double inv_l2) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n > N) return;
+  double sn, cs;
+  sincospi(-(double)n / (double)N, &sn, &cs);  // exp(-2 pi i n / L)
+  const double2 W = make_double2(cs, sn);
+  for (int s = blockIdx.y; s < S; s += gridDim.y) {
+    const double2* zs = Z + (int64_t)s * N;
     const double2 zn = zs[n == N ? 0 : n];
     const double2 zc = zs[n == 0 ? 0 : N - n];
     const double2 zm = make_double2(zc.x, -zc.y);  // conj(Z_{N-n})
     const double2 A = make_double2(0.5 * (zn.x + zm.x), 0.5 * (zn.y + zm.y));
     const double2 D = csub(zn, zm);
     const double2 B = make_double2(0.5 * D.y, -0.5 * D.x);  // D / (2i)
-    double sn, cs;
-    sincospi(-(double)n / (double)N, &sn, &cs);  // exp(-2 pi i n / L)
-    const double2 U = cadd(A, cmul(make_double2(cs, sn), B));
-    sq[i] = (U.x * U.x + U.y * U.y) * inv_l2;
+    const double2 U = cadd(A, cmul(W, B));
+    sq[(int64_t)s * (N + 1) + n] = (U.x * U.x + U.y * U.y) * inv_l2;
   }
 }
 
-// Bin b: mean of sq[s][n] over every sample s and n in [edges[b], edges[b+1]).
+// Mean over the samples of every mode (samples in order).
 __global__ void __launch_bounds__(kBlock)
-    k_sq_bin(const double* __restrict__ sq, int64_t N, int S, const int64_t* __restrict__ edges,
-             double* __restrict__ out) {
-  __shared__ double red[kBlock];
-  const int b = blockIdx.x;
-  const int64_t lo = edges[b], w = edges[b + 1] - lo;
-  const int64_t total = (int64_t)S * w;
+    k_sq_mean(const double* __restrict__ sq, double* __restrict__ mean, int N, int S) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n > N) return;
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < total; e += kBlock) {
-    const int64_t s = e / w;
-    acc += sq[s * (N + 1) + lo + (e - s * w)];
-  }
+  for (int s = 0; s < S; ++s) acc += sq[(int64_t)s * (N + 1) + n];
+  mean[n] = acc / (double)S;
+}
+
+// Chunk c: sum of mean[n] over its modes (fixed order: thread stride, then a
+// tree).
+__global__ void __launch_bounds__(kBlock)
+    k_sq_chunk(const double* __restrict__ mean, const int32_t* __restrict__ chunk_lo, double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  const int c = blockIdx.x;
+  const int lo = chunk_lo[c], hi = chunk_lo[c + 1];
+  double acc = 0.0;
+  for (int n = lo + threadIdx.x; n < hi; n += kBlock) acc += mean[n];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int h = kBlock / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[b] = red[0] / (double)total;
+  if (threadIdx.x == 0) part[c] = red[0];
 }
 
-int grid_for(int64_t total) {
-  const int64_t g = (total + kBlock - 1) / kBlock;
-  return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
+// Bin b: its chunks' sums in order, divided by its number of modes.
+__global__ void __launch_bounds__(kBlock)
+    k_sq_bin(const double* __restrict__ part, const int32_t* __restrict__ chunk_lo,
+             const int32_t* __restrict__ chunk_first, int n_bins, double* __restrict__ out) {
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= n_bins) return;
+  const int c0 = chunk_first[b], c1 = chunk_first[b + 1];
+  double acc = 0.0;
+  for (int c = c0; c < c1; ++c) acc += part[c];
+  out[b] = acc / (double)(chunk_lo[c1] - chunk_lo[c0]);
+}
+
+dim3 grid2(int64_t n, int S) {
+  const unsigned gx = (unsigned)((n + kBlock - 1) / kBlock);
+  return dim3(gx < 1 ? 1 : gx, (unsigned)(S < 65535 ? S : 65535));
 }
 
 }  // namespace
 
 hipError_t launch_sq(const int64_t* off, int S, int64_t L, const double* u_plain, SplitBuf split,
-                     double2* bufA, double2* bufB, const int64_t* edges, int n_bins, double* out,
+                     double2* bufA, double2* bufB, const int32_t* chunk_lo, int n_chunks,
+                     const int32_t* chunk_first, int n_bins, double* part, double* out,
                      hipStream_t st) {
-  const int64_t N = L / 2;
-  int64_t total = (int64_t)S * N;
+  const int N = (int)(L / 2);
+  int lgN = 0;
+  while ((1 << lgN) < N) ++lgN;
   if (u_plain)
-    hipLaunchKernelGGL(k_sq_pack_plain, dim3(grid_for(total)), dim3(kBlock), 0, st, off, u_plain, bufA, N, total);
+    hipLaunchKernelGGL(k_sq_pack_plain, grid2(N, S), dim3(kBlock), 0, st, off, u_plain, bufA, N, S);
   else
-    hipLaunchKernelGGL(k_sq_pack_split, dim3(grid_for(total)), dim3(kBlock), 0, st, off, split.cell, split.frac,
-                       bufA, N, total);
+    hipLaunchKernelGGL(k_sq_pack_split, grid2(N, S), dim3(kBlock), 0, st, off, split.cell, split.frac,
+                       bufA, N, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double2* in = bufA;
   double2* outb = bufB;
-  for (int64_t Ns = 1; Ns < N;) {
-    const int64_t rem = N / Ns;
-    const int R = rem >= 8 ? 8 : (int)rem;
-    const int64_t work = (int64_t)S * (N / R);
-    if (R == 8)
-      hipLaunchKernelGGL((k_fft_pass<8>), dim3(grid_for(work)), dim3(kBlock), 0, st, in, outb, N, Ns, work);
-    else if (R == 4)
-      hipLaunchKernelGGL((k_fft_pass<4>), dim3(grid_for(work)), dim3(kBlock), 0, st, in, outb, N, Ns, work);
+  for (int lgNs = 0; lgNs < lgN;) {
+    const int rem = lgN - lgNs;
+    const int lgR = rem >= 3 ? 3 : rem;
+    const dim3 g = grid2(N >> lgR, S);
+    if (lgR == 3)
+      hipLaunchKernelGGL((k_fft_pass<8>), g, dim3(kBlock), 0, st, in, outb, lgN, lgNs, S);
+    else if (lgR == 2)
+      hipLaunchKernelGGL((k_fft_pass<4>), g, dim3(kBlock), 0, st, in, outb, lgN, lgNs, S);
     else
-      hipLaunchKernelGGL((k_fft_pass<2>), dim3(grid_for(work)), dim3(kBlock), 0, st, in, outb, N, Ns, work);
+      hipLaunchKernelGGL((k_fft_pass<2>), g, dim3(kBlock), 0, st, in, outb, lgN, lgNs, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    Ns *= R;
+    lgNs += lgR;
     double2* t = in;
     in = outb;
     outb = t;
   }
-  // `in` holds the transform; the other buffer takes S rows of N + 1 doubles.
+  // `in` holds the transform; the other buffer takes S rows of N + 1 doubles
+  // and, after them, the per-mode mean over the samples.
   double* sq = reinterpret_cast<double*>(outb);
-  total = (int64_t)S * (N + 1);
-  hipLaunchKernelGGL(k_sq_post, dim3(grid_for(total)), dim3(kBlock), 0, st, in, sq, N, total,
+  double* mean = sq + (int64_t)S * (N + 1);
+  hipLaunchKernelGGL(k_sq_post, grid2(N + 1, S), dim3(kBlock), 0, st, in, sq, N, S,
                      1.0 / ((double)L * (double)L));
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sq_bin, dim3(n_bins), dim3(kBlock), 0, st, sq, N, S, edges, out);
+  hipLaunchKernelGGL(k_sq_mean, grid2(N + 1, 1), dim3(kBlock), 0, st, sq, mean, N, S);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sq_chunk, dim3(n_chunks), dim3(kBlock), 0, st, mean, chunk_lo, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sq_bin, dim3((n_bins + kBlock - 1) / kBlock), dim3(kBlock), 0, st, part, chunk_lo,
+                     chunk_first, n_bins, out);
   return hipGetLastError();
 }
 
