@@ -269,7 +269,43 @@ OTHER_WORKLOADS = {
 }
 
 
+def copy_bandwidth(nbytes, reps=5):
+    """Device-to-device copy rate (read + write bytes per second) of a buffer of nbytes."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    rate = 2.0 * a.numel() * 4 * reps / (time.perf_counter() - t0)
+    del a, b
+    torch.cuda.empty_cache()
+    return rate
+
+
+def plain_without_disorder(qew, args):
+    """The FP64 one-step kernel with no pinning force (a pure stencil, 16 B of
+    HBM traffic per site update) on the L = 2^25 x 5 shape, against the copy
+    bandwidth of a buffer of the same size."""
+    p = dict(workloads.config4(0, n_steps=args.steps), strength=0.0)
+    p["meas_steps"] = np.array([args.steps])
+    out, st, info, wall = time_path(qew, p, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, args.warmup)
+    roof = plain_roofline(st, info, args.steps)
+    copy = copy_bandwidth(int(info.total_sites) * 8)
+    return {"metric": "FP64 one-step stencil without disorder, HBM GB/s", "value": roof["achieved"],
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "site_updates_per_s": round(info.total_sites * args.steps / wall, 1),
+            "copy_gbs": round(copy / 1e9, 1), "of_copy": round(roof["achieved"] * 1e9 / copy, 4),
+            "config": {"workload": "L=2^25 x 5, strength 0, FP64 plain one-step", "buffer_bytes":
+                       int(info.total_sites) * 8}, "roofline": roof}
+
+
 def other_workload(qew, args):
+    if args.workload == "plain0":
+        return plain_without_disorder(qew, args)
     desc, build = OTHER_WORKLOADS[args.workload]
     steps = args.steps
     p = build(steps)
@@ -307,7 +343,7 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output under DIR and exit")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
-    ap.add_argument("--workload", default="c3", choices=sorted(OTHER_WORKLOADS) + ["c3"],
+    ap.add_argument("--workload", default="c3", choices=sorted(OTHER_WORKLOADS) + ["c3", "plain0"],
                     help="c3 (default): the benchmark line; others print one line for that "
                          "workload's FP32 split fused throughput (--steps sets the horizon)")
     args = ap.parse_args()
