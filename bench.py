@@ -47,28 +47,66 @@ OPS_NODE_RB = 68
 HORIZON = 1_000_000
 N_POINTS = 200
 
-KERNEL_SOURCES = ("paper_1211_7275_amd/csrc/qew_kernels.hip", "paper_1211_7275_amd/csrc/qew_device.hpp")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_fused_L2e22x4.md")
 
 
+def _elf_sections(data):
+    """{name: (addr, offset, size)} of a little-endian ELF64 image."""
+    import struct
+    shoff, = struct.unpack_from("<Q", data, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+    hdr = [struct.unpack_from("<IIQQQQIIQQ", data, shoff + i * shentsize) for i in range(shnum)]
+    stroff = hdr[shstrndx][4]
+    out = {}
+    for h in hdr:
+        name = data[stroff + h[0]:data.index(b"\0", stroff + h[0])].decode()
+        out[name] = (h[3], h[4], h[5], h)
+    return out
+
+
 def kernel_source_hash():
-    """sha256 (first 16 hex) of the kernel sources with comments and blank
-    space removed, so that a documentation edit keeps the measured traffic."""
+    """sha256 (first 16 hex) of the machine code of the fused stepping kernel
+    (every k_step_fused instantiation) in the gfx950 code object of the built
+    library: it changes exactly when that kernel's compiled code does."""
     import hashlib
-    import re
+    import struct
+    lib = os.path.join(ROOT, "paper_1211_7275_amd", "lib", "libqew.so")
+    with open(lib, "rb") as fh:
+        data = fh.read()
+    _, off, size, _ = _elf_sections(data)[".hip_fatbin"]
+    blob = data[off:off + size]
+    assert blob[:24] == b"__CLANG_OFFLOAD_BUNDLE__", "unexpected device code bundle"
+    n, = struct.unpack_from("<Q", blob, 24)
+    pos, code = 32, None
+    for _ in range(n):
+        eoff, esize, tlen = struct.unpack_from("<QQQ", blob, pos)
+        triple = blob[pos + 24:pos + 24 + tlen].decode()
+        pos += 24 + tlen
+        if "gfx950" in triple:
+            code = blob[eoff:eoff + esize]
+    assert code is not None, "no gfx950 code object in the library"
+    secs = _elf_sections(code)
+    text_addr, text_off, _, _ = secs[".text"]
+    _, sym_off, sym_size, sym_hdr = secs[".symtab"]
+    _, str_off, _, _ = secs[".strtab"]
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel)) as fh:
-            text = fh.read()
-        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-        text = re.sub(r"//[^\n]*", " ", text)
-        h.update(" ".join(text.split()).encode())
+    syms = []
+    for i in range(sym_size // 24):
+        st_name, st_info, st_other, st_shndx, st_value, st_size = struct.unpack_from(
+            "<IBBHQQ", code, sym_off + 24 * i)
+        name = code[str_off + st_name:code.index(b"\0", str_off + st_name)]
+        if b"k_step_fused" in name and st_size > 0 and not name.endswith(b".kd"):
+            syms.append((name, st_value, st_size))
+    for name, value, size in sorted(syms):
+        start = text_off + (value - text_addr)
+        h.update(name)
+        h.update(code[start:start + size])
     return h.hexdigest()[:16]
 
 
 def committed_traffic(k, tile):
     """HBM bytes per fused launch measured by rocprofv3 (FETCH_SIZE/WRITE_SIZE,
-    copy-calibrated) for this kernel source and geometry, else None."""
+    copy-calibrated) for this kernel code and geometry, else None."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     want = f"k={k} tile={tile} source={kernel_source_hash()}"
@@ -342,7 +380,7 @@ def main():
                     help="only run a 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output under DIR and exit")
-    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--source-hash", action="store_true", help="print the hash of the fused kernel's machine code and exit")
     ap.add_argument("--workload", default="c3", choices=sorted(OTHER_WORKLOADS) + ["c3", "plain0"],
                     help="c3 (default): the benchmark line; others print one line for that "
                          "workload's FP32 split fused throughput (--steps sets the horizon)")

@@ -196,33 +196,32 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 // raw nodes of every site live in LDS, slot-major (node index i * 256 + t).
 // Each sub-step:
 //   1. every site takes one Euler step (neighbours within a thread directly,
-//      across lanes by wave shuffles, across waves through LDS);
+//      across lanes by DPP wave shifts, across waves through a double-buffered
+//      LDS edge array);
 //   2. a site whose cell changed posts a request (its LDS node index, new
 //      cell, old cell) into its wave's region of the request list;
-//   3. barrier; the whole workgroup serves all requests: shift the node
-//      window, generate the missing node (all four after a jump of two or
-//      more cells), store the window, and write the new coefficients into the
-//      request slot;
-//   4. barrier; each requester reads its new coefficients.
-// A sub-step with no request at all skips 3-4.  A wave posts at most
-// kReqPerWave requests per sub-step; the lanes of further requests (a burst
-// of simultaneous cell changes) regenerate their windows themselves.  After nsub <= halo
-// sub-steps the sites within `halo` of either tile end hold garbage (the tile
-// ends reflect), and the valid part [halo, halo + len) is written back with
-// its nodes.  Every value equals what the one-step kernel computes: the
-// float cell differences are exact integers (checked: a tile whose cells
-// spread over 2^23 or more raises the error flag).
+//   3. the same wave serves its requests, lane q taking request q: shift the
+//      node window, generate the missing node (all four after a jump of two
+//      or more cells), store the window, and write the new coefficients into
+//      the request slot; the requesters then read them back.  Requests,
+//      windows and replies belong to one wave and a wave's LDS operations
+//      complete in order, so this needs no workgroup barrier;
+//   4. the wave publishes its end sites; one workgroup barrier.
+// A wave posts at most kReqPerWave requests per sub-step; the lanes of further
+// requests (a burst of simultaneous cell changes) regenerate their windows
+// themselves.  After nsub <= halo sub-steps the sites within `halo` of either
+// tile end hold garbage (the tile ends reflect), and the valid part
+// [halo, halo + len) is written back with its nodes.  Every value equals what
+// the one-step kernel computes: the float cell differences are exact integers
+// (checked: a tile whose cells spread over 2^23 or more raises the error flag).
 // ---------------------------------------------------------------------------
-#ifndef QEW_REQ_PER_WAVE
-#define QEW_REQ_PER_WAVE 64
-#endif
-#ifndef QEW_FUSED_MIN_WAVES
-#define QEW_FUSED_MIN_WAVES 4
-#endif
-constexpr int kReqPerWave = QEW_REQ_PER_WAVE;
+constexpr int kReqPerWave = 64;
+
+// Waves per SIMD the register allocation must allow (LDS allows the same).
+constexpr int fused_min_waves(int P) { return P == 6 ? 5 : (P <= 8 ? 4 : (P == 12 ? 3 : 2)); }
 
 template <int KIND, int P>
-__global__ void __launch_bounds__(kBlock, P == 6 ? 5 : (P <= 8 ? QEW_FUSED_MIN_WAVES : (P == 12 ? 3 : 2)))
+__global__ void __launch_bounds__(kBlock, fused_min_waves(P))
     k_step_fused(Tables t, SplitBuf in, SplitBuf out, Phys ph, int halo, int nsub) {
   constexpr int T = kBlock * P;
   constexpr int NW = kBlock / 64;
