@@ -17,7 +17,7 @@ struct Tables {
   const int32_t* mt_p0;     //        first site
   const int32_t* mt_len;    //        sites
   const int32_t* mt_first;  // [S+1] first measurement tile of each sample
-  const int32_t* ft_s;      // [n_ft] fused wave tiles: sample
+  const int32_t* ft_s;      // [n_ft] fused workgroup tiles: sample
   const int32_t* ft_p0;     //        first valid site
   const int32_t* ft_len;    //        valid sites
   int32_t n_mt;

@@ -2,9 +2,10 @@
 //
 // A plan holds the validated problem, the per-sample offsets of the state
 // buffers, two tile work lists (measurement / one-step tiles of fixed size,
-// and fused wave tiles whose valid width depends on the blocking depth k),
+// and fused workgroup tiles whose valid width depends on the blocking depth k),
 // and the layout of the caller's workspace.  qew_run walks the measurement
-// steps: at each one it reduces Eqs. (3)-(5) of the state, and between them
+// steps: at each one it reduces Eqs. (3)-(5) of the state (and, when the
+// problem asks for it, the structure factor of Eq. (6)), and between them
 // it advances the chains by Euler steps (Eq. (1), Sec. III B), one or k steps
 // per launch, replaying captured hipGraphs of 16 launches where it can.
 #include <hip/hip_runtime.h>
