@@ -144,6 +144,26 @@ def fscan(kind, L, drives, n_steps, n_meas, seed, disorders=1, precision=None, p
     return {"t": t, "drives": drives, "v": v, "w2": w2, "f_lo": f_lo, "f_hi": f_hi, "signs": signs}
 
 
+def exponents(t, v, w2, t0s=(1.0, 10.0, 100.0, 1000.0, 10000.0), t_mic=2.0):
+    """The exponent estimates of Sec. IV E for one drive's series: beta/(nu z)
+    from v and 1 - zeta/z from w = sqrt(w2), by pure power laws on [t0, 4 t0]
+    (procedure (c)) and by the corrected forms for t >= t_mic (procedure (a)),
+    with gamma(t) at the end of each window."""
+    t = np.asarray(t, np.float64)
+    w = np.sqrt(np.asarray(w2, np.float64))
+    t0s = [t0 for t0 in t0s if 4 * t0 <= t[-1]]
+    out = {"t0": list(t0s),
+           "beta_over_nu_z": (-window_exponents(t, v, t0s)).tolist(),
+           "one_minus_zeta_over_z": (1.0 - window_exponents(t, w, t0s)).tolist(),
+           "gamma": [float(np.interp(4 * t0, t, gamma(t, w2, v))) for t0 in t0s]}
+    try:
+        out["corrected_beta_over_nu_z"] = -corrected_fit(t, v, t_mic)["e"]
+        out["corrected_one_minus_zeta_over_z"] = 1.0 - corrected_fit(t, w, t_mic)["e"]
+    except (RuntimeError, ValueError):
+        pass
+    return out
+
+
 def main(argv=None):
     """Command line f-scan: a geometric coarse scan over [--f-min, --f-max]
     locates the threshold, then a scan in steps of --f-step between the last
@@ -163,7 +183,20 @@ def main(argv=None):
     ap.add_argument("--points", type=int, default=100)
     ap.add_argument("--disorders", type=int, default=1)
     ap.add_argument("--seed", type=int, default=workloads.SEED_BASE + 4)
+    ap.add_argument("--decay", type=float, nargs="+", metavar="F",
+                    help="instead of a scan: run these drives and report the exponents of v and w")
     a = ap.parse_args(argv)
+    if a.decay:
+        r = fscan(a.kind, a.L, a.decay, a.steps, a.points, a.seed, disorders=a.disorders)
+        res = []
+        for i, f in enumerate(r["drives"]):
+            e = exponents(r["t"], r["v"][i], r["w2"][i])
+            e["f"] = float(f)
+            e["class"] = int(r["signs"][i])
+            res.append(e)
+        print(json.dumps({"kind": a.kind, "L": a.L, "steps": a.steps, "disorders": a.disorders,
+                          "drives": res}))
+        return
 
     def describe(r):
         late = [late_slope(r["t"], v) if v[-1] > 0 else None for v in r["v"]]

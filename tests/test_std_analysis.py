@@ -86,3 +86,16 @@ def test_bracket_fc_on_oracle_series(oracle):
         v.append(oracle.run(p)["v"].mean(0))
     f_lo, f_hi, signs = std.bracket_fc(drives, meas * 0.05, np.array(v))
     assert (f_lo, f_hi) == (0.3, 2.0)
+
+
+def test_exponents_of_a_corrected_critical_decay():
+    """The exponent report of one drive: windowed estimates converge to the
+    exponents of corrected power laws, the corrected fits return them."""
+    e = 0.128
+    v = 0.721 * T ** -e * (1 + (T / 0.110) ** -0.715)
+    w = 0.839 * T ** (1 - e) * (1 + (T / 0.485) ** -0.712)
+    r = std.exponents(T, v, w ** 2)
+    assert r["beta_over_nu_z"][-1] == pytest.approx(e, abs=2e-4)
+    assert r["one_minus_zeta_over_z"][-1] == pytest.approx(e, abs=5e-4)
+    assert r["corrected_beta_over_nu_z"] == pytest.approx(e, abs=1e-6)
+    assert r["corrected_one_minus_zeta_over_z"] == pytest.approx(e, abs=1e-6)
