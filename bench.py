@@ -191,10 +191,19 @@ def cpu_baseline(p, seconds_target=15.0):
     t0 = time.perf_counter()
     oracle.run_sample(p["kind"], p["strength"], p["seed"], 0, L, p["c"], p["dt"], 1.0, steps, [])
     dt = time.perf_counter() - t0
+    # the same sample on one core, a few steps
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.run_sample(p["kind"], p["strength"], p["seed"], 0, L, p["c"], p["dt"], 1.0, 4, [])
+        single = L * 4 / (time.perf_counter() - t1)
+    finally:
+        oracle.set_threads(threads)
     return {"value": round(L * steps / dt, 1), "unit": "site-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"1 of the 4 samples (L=2^22), {steps} Euler steps from the flat start, "
-                      f"FP64, OpenMP over sites, {dt:.1f} s"}
+                      f"FP64, OpenMP over sites, {dt:.1f} s",
+            "single_core_value": round(single, 1)}
 
 
 def parity_check(qew):
