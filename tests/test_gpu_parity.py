@@ -665,3 +665,26 @@ def test_critical_forces_match_oracle(qew, oracle, kind):
         assert abs(r["f_lo"][s] - ref["f_lo"]) <= tol_f
         if r["f_lo"][s] == ref["f_lo"]:
             assert np.max(np.abs(r["u_c"][s] - ref["u_c"])) <= 1e-6
+
+
+def test_structure_factor_resume_and_errors(qew):
+    """Measurements before a restored step read NaN; the rest equal an
+    uninterrupted run; asking a problem without bins for S_q is an error."""
+    L, N, H = 256, 300, 120
+    meas = [0, 50, 120, 200, 300]
+    edges = workloads.sq_edges_log(L, 8)
+    p = workloads.custom(0, [L] * 2, 1.0, N, meas, SEED + 80, sq_edges=edges)
+    full, _ = _sq_gpu(qew, p, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP)
+    half = run_gpu(qew, dict(p, n_steps=H, meas_steps=[0, 50, 120]), qew.QEW_FP64_PLAIN,
+                   qew.QEW_ONE_STEP)
+    rest, _ = _sq_gpu(qew, p, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, states=half["u"], step=H)
+    assert np.all(np.isnan(rest[:2]))
+    assert np.array_equal(rest[2:], full[2:])
+    plain = workloads.custom(0, [L], 1.0, 10, [10], SEED)
+    sim = qew.Simulation(plain, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_ONE_STEP)
+    try:
+        sim.run()
+        with pytest.raises(qew.QewError):
+            qew.qew_sq_get(sim.plan, sim.ws, 1, 1)
+    finally:
+        sim.close()
