@@ -333,11 +333,13 @@ def copy_bandwidth(nbytes, reps=5):
     return rate
 
 
-def plain_without_disorder(qew, args):
+def plain_without_disorder(qew, args, small=False):
     """The FP64 one-step kernel with no pinning force (a pure stencil, 16 B of
-    HBM traffic per site update) on the L = 2^25 x 5 shape, against the copy
-    bandwidth of a buffer of the same size."""
-    p = dict(workloads.config4(0, n_steps=args.steps), strength=0.0)
+    HBM traffic per site update) on the L = 2^25 x 5 shape (small: the
+    benchmark's 2^22 x 4, whose two 128 MiB buffers come close to the 256 MB
+    Infinity Cache), against the copy bandwidth of a buffer of the same size."""
+    base = workloads.config3(n_steps=args.steps) if small else workloads.config4(0, n_steps=args.steps)
+    p = dict(base, strength=0.0)
     p["meas_steps"] = np.array([args.steps])
     out, st, info, wall = time_path(qew, p, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, args.warmup)
     roof = plain_roofline(st, info, args.steps)
@@ -346,13 +348,14 @@ def plain_without_disorder(qew, args):
             "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "site_updates_per_s": round(info.total_sites * args.steps / wall, 1),
             "copy_gbs": round(copy / 1e9, 1), "of_copy": round(roof["achieved"] * 1e9 / copy, 4),
-            "config": {"workload": "L=2^25 x 5, strength 0, FP64 plain one-step", "buffer_bytes":
+            "config": {"workload": ("L=2^22 x 4" if small else "L=2^25 x 5") +
+                       ", strength 0, FP64 plain one-step", "buffer_bytes":
                        int(info.total_sites) * 8}, "roofline": roof}
 
 
 def other_workload(qew, args):
-    if args.workload == "plain0":
-        return plain_without_disorder(qew, args)
+    if args.workload in ("plain0", "plain0small"):
+        return plain_without_disorder(qew, args, small=args.workload == "plain0small")
     desc, build = OTHER_WORKLOADS[args.workload]
     steps = args.steps
     p = build(steps)
@@ -390,7 +393,7 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output under DIR and exit")
     ap.add_argument("--source-hash", action="store_true", help="print the hash of the fused kernel's machine code and exit")
-    ap.add_argument("--workload", default="c3", choices=sorted(OTHER_WORKLOADS) + ["c3", "plain0"],
+    ap.add_argument("--workload", default="c3", choices=sorted(OTHER_WORKLOADS) + ["c3", "plain0", "plain0small"],
                     help="c3 (default): the benchmark line; others print one line for that "
                          "workload's FP32 split fused throughput (--steps sets the horizon)")
     args = ap.parse_args()
