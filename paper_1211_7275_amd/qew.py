@@ -275,6 +275,13 @@ class Simulation:
             qew_plan_destroy(self.plan)
             self.plan = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
             self.close()
