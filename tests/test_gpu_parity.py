@@ -511,11 +511,14 @@ def test_full_size_l2e25_sampled_sites(qew, oracle, kind):
     assert np.max(np.abs(d - 0.05 * out["v"][:, :-1])) <= 1e-6
 
 
-def test_full_size_l2e22_fp64_plain_sampled_sites(qew, oracle):
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_full_size_l2e22_fp64_plain_sampled_sites(qew, oracle, kind):
+    """The FP64 one-step path at L = 2^22 x 4 for every disorder kind: sampled
+    sites against the oracle's light-cone windows."""
     N = 12
-    p = workloads.config3(n_steps=N, n_meas=2)
+    p = dict(workloads.config3(n_steps=N, n_meas=2), kind=kind)
     L = int(p["L"][0])
-    say("full size L=2^22 x 4, fp64 plain, 12 steps")
+    say("full size L=2^22 x 4, fp64 plain, 12 steps, kind", kind)
     sim = qew.Simulation(p, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_ONE_STEP)
     try:
         sim.run()
@@ -523,8 +526,31 @@ def test_full_size_l2e22_fp64_plain_sampled_sites(qew, oracle):
     finally:
         sim.close()
     for jj in (0, 1, 4095, 4096, L - 1, 123457, 3_000_001):
-        ref = oracle.site_after(0, 1.0, p["seed"], 1, L, jj, 1.0, 0.05, 1.0, N)
+        ref = oracle.site_after(kind, 1.0, p["seed"], 1, L, jj, 1.0, 0.05, 1.0, N)
         assert abs(u[jj] - ref) <= 1e-12
+
+
+@pytest.mark.parametrize("kind,period", [(1, 0), (0, 1000)])
+def test_full_size_l2e22_fused_other_media(qew, oracle, kind, period):
+    """The fused path at L = 2^22 x 4 (autotuned) with RB disorder and with a
+    medium periodic in u: sampled sites against the oracle's light-cone windows."""
+    N = 40
+    p = dict(workloads.config3(n_steps=N, n_meas=2), kind=kind, period=period)
+    L = int(p["L"][0])
+    say("full size L=2^22 x 4, fused, kind", kind, "period", period)
+    sim = qew.Simulation(p, precision=qew.QEW_FP32_SPLIT, path=qew.QEW_FUSED)
+    try:
+        sim.run()
+        info = sim.info()
+        V = info.tile - 2 * info.k
+        rng = np.random.default_rng(5)
+        for s in (1, 2):
+            u, _ = sim.read_state(s)
+            for jj in sorted({0, L - 1, V - 1, V, L // 3} | set(rng.integers(0, L, 8))):
+                ref = oracle.site_after(kind, 1.0, p["seed"], s, L, jj, 1.0, 0.05, 1.0, N, period)
+                assert abs(u[jj] - ref) <= 1e-4, (s, jj)
+    finally:
+        sim.close()
 
 
 # ------------------------------------------------------------- edge cases --
