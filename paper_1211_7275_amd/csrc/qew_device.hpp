@@ -27,17 +27,26 @@ constexpr int kRB = 1;     // random bond, Gaussian potential, Catmull-Rom
 constexpr int kRBLin = 2;  // random bond, Gaussian potential, linear spline (Case 3)
 constexpr int kRFPc = 3;   // random field, Gaussian forces, no interpolation (Case 4)
 
+// Three-input exclusive or in one VALU instruction (v_bitop3_b32 with the
+// truth table of a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
-// products with the Weyl-bumped key.  The 64-bit product maps to one
-// v_mad_u64_u32 per multiply on CDNA.
+// products with the Weyl-bumped key.  A round is two v_mad_u64_u32 and two
+// three-input xors.  The first two rounds keep plain xors: the disorder's
+// counters have wave-uniform words (sample id, 0) whose share of those rounds
+// the compiler then computes on the scalar unit.
 __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
                                               uint32_t& x3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * (uint64_t)x0;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * (uint64_t)x2;
-    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    const uint32_t h0 = (uint32_t)(p0 >> 32), h1 = (uint32_t)(p1 >> 32);
+    const uint32_t y0 = r < 2 ? h1 ^ x1 ^ k0 : xor3(h1, x1, k0);
+    const uint32_t y2 = r < 2 ? h0 ^ x3 ^ k1 : xor3(h0, x3, k1);
     x1 = (uint32_t)p1;
     x3 = (uint32_t)p0;
     x0 = y0;

@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
   constexpr int NW = kBlock / 64;
   constexpr int RQ = kReqPerWave;
   __shared__ float4 s_nodes[T];
-  __shared__ int4 s_req[NW * RQ];
+  __shared__ int4 s_req[NW * (RQ + 1)];  // per wave: RQ requests, then one sink slot
   __shared__ float2 s_edge[2][NW][2];
 
   const int tid = threadIdx.x;
@@ -333,15 +333,12 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       }
 
       // Euler step of every site (Jacobi: old values of the neighbours); a
-      // site that changed cell posts a request.  Byte i % 4 of rk[i / 4]
-      // holds k + 1 for the request of slot i (k: index in this wave's
-      // region), 0 if none; a site whose request does not fit the region is
-      // marked in `pending` and served by its own lane below.
-      uint32_t rk[(P + 3) / 4];
-#pragma unroll
-      for (int v = 0; v < (P + 3) / 4; ++v) rk[v] = 0u;
-      uint32_t pending = 0u;
+      // site that changed cell posts a request at index kq[i] of this wave's
+      // region.  Requests past the region's RQ entries go to its sink slot
+      // and are served by their own lane below.
+      uint32_t kq[P];
       uint32_t nreq = 0u;  // wave-uniform
+      const int rbase = wv * (RQ + 1);
       float oc[P];          // cells before the step
       float dl = c[0] - cle;  // cell difference to the left neighbour
       float pr = rle;
@@ -363,14 +360,10 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       for (int i = 0; i < P; ++i) {
         const bool mv = c[i] != oc[i];
         const uint64_t moved = __ballot(mv);
+        kq[i] = min(nreq + mbcnt64(moved), (uint32_t)RQ);
         if (mv) {
-          const uint32_t k = nreq + mbcnt64(moved);
-          if (k < (uint32_t)RQ) {
-            s_req[wv * RQ + k] = make_int4(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc[i]), 0);
-            rk[i / 4] |= (k + 1u) << (8 * (i % 4));
-          } else {
-            pending |= 1u << i;
-          }
+          *reinterpret_cast<int3*>(&s_req[rbase + (int)kq[i]]) =
+              make_int3(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc[i]));
         }
         nreq += (uint32_t)__popcll(moved);
       }
@@ -382,13 +375,13 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       if (nserve > 0u) {
         __builtin_amdgcn_wave_barrier();
         if ((uint32_t)lane < nserve) {
-          const int slot = wv * RQ + lane;
+          const int slot = rbase + lane;
           const int4 rq = s_req[slot];  // {node index, new cell, old cell} (cells relative to cbase)
           const int ni = rq.x;
           const float cnew = __int_as_float(rq.y);
           const float move = cnew - __int_as_float(rq.z);
           const int32_t cell = cbase + (int32_t)cnew;
-          const int lp = (ni % kBlock) * P + ni / kBlock;  // tile-local position
+          const int lp = (int)(((uint32_t)ni % kBlock) * P + (uint32_t)ni / kBlock);  // tile-local position
           int j = start_mod + lp;
           if (j >= L) j -= L;
           if (j >= L) j %= L;
@@ -410,24 +403,24 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        // Requesters read their new coefficients.
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-          const uint32_t k1 = (rk[i / 4] >> (8 * (i % 4))) & 0xffu;
-          if (k1 != 0u) {
-            const int4 v = s_req[wv * RQ + (int)k1 - 1];
-            a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
-                               __int_as_float(v.w));
-          }
-        }
-        __builtin_amdgcn_wave_barrier();
       }
-      // Rare: requests beyond the region (a burst of cell changes) are served
-      // by their own lane: regenerate the window of the new cell.
-      if (__ballot(pending != 0u)) {
+      // Requesters read their new coefficients (a request past the region
+      // reads its sink slot and is redone below).
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        if (c[i] != oc[i]) {
+          const int4 v = s_req[rbase + (int)kq[i]];
+          a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
+                             __int_as_float(v.w));
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      // Rare: more requests than the region holds (a burst of cell changes).
+      // Those past it regenerate their window on their own lane.
+      if (nreq > (uint32_t)RQ) {
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-          if ((pending >> i) & 1u) {
+          if (c[i] != oc[i] && kq[i] == (uint32_t)RQ) {
             int j = start_mod + tid * P;
             asm volatile("" : "+v"(j));  // keep this rare path's index arithmetic here
             j += i;
