@@ -37,14 +37,14 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
 }
 
 // Wave-wide lane shifts by one (DPP wave_shr:1 / wave_shl:1): lane l receives
-// x of lane l - 1 (resp. l + 1); lane 0 (resp. 63) keeps its own x.
+// x of lane l - 1 (resp. l + 1); lane 0 (resp. 63) receives 0.
 __device__ __forceinline__ float from_lower_lane(float x) {
   const int v = __float_as_int(x);
-  return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float from_upper_lane(float x) {
   const int v = __float_as_int(x);
-  return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
@@ -304,8 +304,9 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
     if (lane == 63) s_edge[0][wv][1] = make_float2(c[P - 1], r[P - 1]);
     __syncthreads();
 
-    for (int sub = 0; sub < nsub; ++sub) {
-      const int par = sub & 1;
+    // One sub-step; the loop runs it twice per trip so that the state
+    // arrays alternate between two register sets without copies.
+    auto substep = [&](const int par) __attribute__((always_inline)) {
       // Neighbours of this thread's end sites.  The tile ends reflect.
       float cle = from_lower_lane(c[P - 1]);
       float rle = from_lower_lane(r[P - 1]);
@@ -440,7 +441,13 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       if (lane == 0) s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
       if (lane == 63) s_edge[par ^ 1][wv][1] = make_float2(c[P - 1], r[P - 1]);
       __syncthreads();
+    };
+    int sub = 0;
+    for (; sub + 2 <= nsub; sub += 2) {
+      substep(0);
+      substep(1);
     }
+    if (sub < nsub) substep(0);
 
     // Write the valid part: tile-local q in [halo, halo + len).
     int qb = tid * P;
