@@ -334,12 +334,14 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       }
 
       // Euler step of every site (Jacobi: old values of the neighbours); a
-      // site that changed cell posts a request at index kq[i] of this wave's
-      // region.  Requests past the region's RQ entries go to its sink slot
-      // and are served by their own lane below.
-      uint32_t kq[P];
+      // site that changed cell posts a request into this wave's region, at
+      // byte offset kb[i] of s_req.  Requests past the region's RQ entries go
+      // to its sink slot and are served by their own lane below.
+      uint32_t kb[P];
       uint32_t nreq = 0u;  // wave-uniform
       const int rbase = wv * (RQ + 1);
+      const uint32_t rbase_b = (uint32_t)rbase * (uint32_t)sizeof(int4);
+      const uint32_t sink_b = rbase_b + (uint32_t)RQ * (uint32_t)sizeof(int4);
       float oc[P];          // cells before the step
       float dl = c[0] - cle;  // cell difference to the left neighbour
       float pr = rle;
@@ -361,12 +363,17 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       for (int i = 0; i < P; ++i) {
         const bool mv = c[i] != oc[i];
         const uint64_t moved = __ballot(mv);
-        kq[i] = min(nreq + mbcnt64(moved), (uint32_t)RQ);
+        const uint32_t cnt = (uint32_t)__popcll(moved);
+        // The wave-uniform part stays one scalar operand of the address;
+        // requests past the region land in its sink slot.
+        kb[i] = min(mbcnt64(moved) * (uint32_t)sizeof(int4) +
+                        (uint32_t)uniform_i32((int)(rbase_b + nreq * (uint32_t)sizeof(int4))),
+                    sink_b);
         if (mv) {
-          *reinterpret_cast<int3*>(&s_req[rbase + (int)kq[i]]) =
+          *reinterpret_cast<int3*>(reinterpret_cast<char*>(s_req) + kb[i]) =
               make_int3(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc[i]));
         }
-        nreq += (uint32_t)__popcll(moved);
+        nreq += cnt;
       }
       // Serve this wave's requests with this wave's lanes: lane q takes request
       // q.  The requests, their node windows and the replies belong to this
@@ -410,7 +417,7 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         if (c[i] != oc[i]) {
-          const int4 v = s_req[rbase + (int)kq[i]];
+          const int4 v = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(s_req) + kb[i]);
           a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
                              __int_as_float(v.w));
         }
@@ -421,7 +428,7 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       if (nreq > (uint32_t)RQ) {
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-          if (c[i] != oc[i] && kq[i] == (uint32_t)RQ) {
+          if (c[i] != oc[i] && kb[i] == sink_b) {
             int j = start_mod + tid * P;
             asm volatile("" : "+v"(j));  // keep this rare path's index arithmetic here
             j += i;
