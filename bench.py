@@ -183,10 +183,12 @@ def cpu_baseline(p, seconds_target=15.0):
 
     threads = oracle.get_threads()
     L = int(p["L"][0])
-    # one sample, full length, as many steps as fit the time target
-    t0 = time.perf_counter()
+    # one sample, full length, as many steps as fit the time target (the step
+    # time is taken from a 4-step run after a 1-step warm-up of the threads)
     oracle.run_sample(p["kind"], p["strength"], p["seed"], 0, L, p["c"], p["dt"], 1.0, 1, [])
-    per_step = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.run_sample(p["kind"], p["strength"], p["seed"], 0, L, p["c"], p["dt"], 1.0, 4, [])
+    per_step = (time.perf_counter() - t0) / 4
     steps = max(1, int(seconds_target / max(per_step, 1e-6)))
     t0 = time.perf_counter()
     oracle.run_sample(p["kind"], p["strength"], p["seed"], 0, L, p["c"], p["dt"], 1.0, steps, [])
