@@ -178,7 +178,8 @@ def test_ensemble_on_device(qew, c0_oracle):
 
 # -------------------------------------------- fused == one-step (bitwise) --
 
-GEOMS = [(1, 1024), (5, 1024), (8, 1024), (13, 1536), (32, 1536), (16, 2048), (32, 2048), (32, 4096), (64, 4096)]
+GEOMS = [(1, 1024), (5, 1024), (8, 1024), (13, 1536), (32, 1536), (16, 2048), (32, 2048), (7, 3072),
+         (64, 3072), (32, 4096), (64, 4096)]
 SIZES = [3, 5, 31, 64, 100, 511, 1000, 1024, 1500, 5000]
 
 
@@ -365,10 +366,15 @@ def test_zero_disorder_flat_line(qew):
     """strength 0, flat start: the line moves rigidly, v = f exactly, w2 = 0."""
     N = 500
     p = workloads.custom(0, [1000, 4096], [1.0, 0.5], N, [0, 1, 10, 499, 500], SEED, strength=0.0)
-    for prec, path in [(qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP), (qew.QEW_FP32_SPLIT, qew.QEW_FUSED),
-                       (qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP)]:
-        say("flat line, strength 0", prec, path)
-        out = run_gpu(qew, p, prec, path, k=16 if path else 0, tile=1024 if path else 0)
+    # every site of a wave changes cell in the same step: the fused kernel's
+    # requests overflow the per-wave region, on every tile width
+    for prec, path, k, tile in [(qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 0, 0),
+                                (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 16, 1024),
+                                (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 64, 2048),
+                                (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 64, 3072),
+                                (qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP, 0, 0)]:
+        say("flat line, strength 0", prec, path, k, tile)
+        out = run_gpu(qew, p, prec, path, k=k, tile=tile)
         assert np.all(out["v"] == np.array([[1.0], [0.5]]))
         assert np.all(out["w2"] == 0.0)
         for s, f in enumerate((1.0, 0.5)):
