@@ -132,13 +132,14 @@ __global__ void __launch_bounds__(kBlock)
   const uint32_t id = t.did[s];
   const double f = t.f[s];
   const PlainPhys pp{ph.c, ph.dt, ph.strength};
+  const VectorKeys keys = vector_keys(ph.k0, ph.k1);
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
     const int jm = (j == 0) ? L - 1 : j - 1;
     const int jp = (j == L - 1) ? 0 : j + 1;
     const double u = uin[base + j];
-    const double F = plain_force<KIND>(uin[base + jm], u, uin[base + jp], (uint32_t)j, id, ph.k0,
-                                       ph.k1, f, ph.period, pp);
+    const double F = plain_force<KIND>(uin[base + jm], u, uin[base + jp], (uint32_t)j, id, keys, f,
+                                       ph.period, pp);
     uout[base + j] = u + ph.dt * F;
   }
 }
@@ -515,6 +516,7 @@ __global__ void __launch_bounds__(kBlock)
   const uint32_t id = t.did[s];
   const double f = t.f[s];
   const PlainPhys pp{ph.c, ph.dt, ph.strength};
+  const VectorKeys keys = vector_keys(ph.k0, ph.k1);
   const double K = u[base + p0];  // shift: the tile's first site (exactly 0 for a flat tile)
   double sf = 0.0, s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < len; q += kBlock) {
@@ -522,7 +524,7 @@ __global__ void __launch_bounds__(kBlock)
     const int jm = (j == 0) ? L - 1 : j - 1;
     const int jp = (j == L - 1) ? 0 : j + 1;
     const double uj = u[base + j];
-    sf += plain_force<KIND>(u[base + jm], uj, u[base + jp], (uint32_t)j, id, ph.k0, ph.k1, f, ph.period,
+    sf += plain_force<KIND>(u[base + jm], uj, u[base + jp], (uint32_t)j, id, keys, f, ph.period,
                             pp);
     const double x = uj - K;
     s1 += x;
