@@ -33,23 +33,34 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-// Philox4x32-10 round keys.  ScalarKeys bumps the key by the Weyl constants
-// round by round (wave-uniform: the bumps run on the scalar unit).
-// VectorKeys holds the ten round keys in vector registers, for kernels with
-// registers to spare: a three-input xor on vector registers issues faster than
-// one with a scalar-register operand on gfx950.
-struct ScalarKeys {
-  uint32_t k0, k1;
-  static constexpr bool kVector = false;
-  __device__ __forceinline__ uint32_t a(int r) const { return k0 + (uint32_t)r * kWeyl0; }
-  __device__ __forceinline__ uint32_t b(int r) const { return k1 + (uint32_t)r * kWeyl1; }
-};
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// products with the Weyl-bumped key.  A round is two v_mad_u64_u32 and two
+// three-input xors.  The first two rounds keep plain xors: the disorder's
+// counters have wave-uniform words (sample id, 0) whose share of those rounds
+// the compiler then computes on the scalar unit.
+__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
+                                              uint32_t& x3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * (uint64_t)x2;
+    const uint32_t h0 = (uint32_t)(p0 >> 32), h1 = (uint32_t)(p1 >> 32);
+    const uint32_t y0 = r < 2 ? h1 ^ x1 ^ k0 : xor3(h1, x1, k0);
+    const uint32_t y2 = r < 2 ? h0 ^ x3 ^ k1 : xor3(h0, x3, k1);
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+    k0 += kWeyl0;
+    k1 += kWeyl1;
+  }
+}
 
+// The ten round keys in vector registers, for kernels with registers to
+// spare: a three-input xor on vector registers issues faster than one with a
+// scalar-register operand on gfx950.
 struct VectorKeys {
   uint32_t k0[10], k1[10];
-  static constexpr bool kVector = true;
-  __device__ __forceinline__ uint32_t a(int r) const { return k0[r]; }
-  __device__ __forceinline__ uint32_t b(int r) const { return k1[r]; }
 };
 
 __device__ __forceinline__ VectorKeys vector_keys(uint32_t k0, uint32_t k1) {
@@ -64,32 +75,20 @@ __device__ __forceinline__ VectorKeys vector_keys(uint32_t k0, uint32_t k1) {
   return v;
 }
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
-// products with the Weyl-bumped key.  A round is two v_mad_u64_u32 and two
-// three-input xors.  With scalar keys the first two rounds keep plain xors:
-// the disorder's counters have wave-uniform words (sample id, 0) whose share
-// of those rounds the compiler then computes on the scalar unit.
-template <class Keys>
+// The same generator with the round keys of `keys`.
 __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
-                                              uint32_t& x3, const Keys& keys) {
+                                              uint32_t& x3, const VectorKeys& keys) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * (uint64_t)x0;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * (uint64_t)x2;
-    const uint32_t h0 = (uint32_t)(p0 >> 32), h1 = (uint32_t)(p1 >> 32);
-    const bool plain = !Keys::kVector && r < 2;
-    const uint32_t y0 = plain ? h1 ^ x1 ^ keys.a(r) : xor3(h1, x1, keys.a(r));
-    const uint32_t y2 = plain ? h0 ^ x3 ^ keys.b(r) : xor3(h0, x3, keys.b(r));
+    const uint32_t y0 = xor3((uint32_t)(p1 >> 32), x1, keys.k0[r]);
+    const uint32_t y2 = xor3((uint32_t)(p0 >> 32), x3, keys.k1[r]);
     x1 = (uint32_t)p1;
     x3 = (uint32_t)p0;
     x0 = y0;
     x2 = y2;
   }
-}
-
-__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
-                                              uint32_t& x3, uint32_t k0, uint32_t k1) {
-  philox4x32_10(x0, x1, x2, x3, ScalarKeys{k0, k1});
 }
 
 // Raw words of the disorder generator at (j, n): counter (j, (uint32)n, id, 0),
@@ -104,16 +103,17 @@ __device__ __forceinline__ int32_t wrap_cell(int32_t n, int32_t period) {
   return m < 0 ? m + period : m;
 }
 
-template <class Keys>
-__device__ __forceinline__ NodeWords node_words(uint32_t j, int32_t n, uint32_t id, const Keys& keys) {
+__device__ __forceinline__ NodeWords node_words(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
+                                                uint32_t k1) {
   uint32_t x0 = j, x1 = (uint32_t)n, x2 = id, x3 = 0u;
-  philox4x32_10(x0, x1, x2, x3, keys);
+  philox4x32_10(x0, x1, x2, x3, k0, k1);
   return {x0, x1};
 }
 
-__device__ __forceinline__ NodeWords node_words(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
-                                                uint32_t k1) {
-  return node_words(j, n, id, ScalarKeys{k0, k1});
+__device__ __forceinline__ NodeWords node_words(uint32_t j, int32_t n, uint32_t id, const VectorKeys& keys) {
+  uint32_t x0 = j, x1 = (uint32_t)n, x2 = id, x3 = 0u;
+  philox4x32_10(x0, x1, x2, x3, keys);
+  return {x0, x1};
 }
 
 // Random-field force value: 24 random bits m = x0 >> 8 mapped to the odd
@@ -155,10 +155,10 @@ __device__ __forceinline__ float node_f32(uint32_t j, int32_t n, uint32_t id, ui
   }
 }
 
-template <int KIND, class Keys>
-__device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, const Keys& keys,
-                                           int32_t period) {
-  const NodeWords w = node_words(j, wrap_cell(n, period), id, keys);
+template <int KIND>
+__device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
+                                           uint32_t k1, int32_t period) {
+  const NodeWords w = node_words(j, wrap_cell(n, period), id, k0, k1);
   if constexpr (KIND == kRF) {
     return (double)rf_odd(w.x0) * 0x1p-24;
   } else {
@@ -167,9 +167,14 @@ __device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, c
 }
 
 template <int KIND>
-__device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
-                                           uint32_t k1, int32_t period) {
-  return node_f64<KIND>(j, n, id, ScalarKeys{k0, k1}, period);
+__device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, const VectorKeys& keys,
+                                           int32_t period) {
+  const NodeWords w = node_words(j, wrap_cell(n, period), id, keys);
+  if constexpr (KIND == kRF) {
+    return (double)rf_odd(w.x0) * 0x1p-24;
+  } else {
+    return rb_value_f64(w.x0, w.x1);
+  }
 }
 
 // ---------------------------------------------------------------------------
