@@ -14,10 +14,10 @@
 //                  per thread), `halo` of them on each side recomputed
 //                  redundantly; the four nodes of each site's cell stay in
 //                  LDS (and in HBM between launches).  A site whose cell
-//                  changes needs one new node; the workgroup gathers those
-//                  requests into LDS and generates them with all its lanes,
-//                  so Philox costs a fraction of a pass per sub-step instead
-//                  of one per changed site slot.
+//                  changes needs one new node; each wave gathers its sites'
+//                  requests into LDS and serves them with its own lanes, so
+//                  Philox costs one pass per wave and sub-step instead of
+//                  one per changed site slot.
 //   k_meas_*       per-tile FP64 partials of sum F, sum (u-K), sum (u-K)^2.
 //   k_meas_final   per-sample combine (Chan et al. pairwise update) into
 //                  v, ubar, w2.
