@@ -421,16 +421,19 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
         __builtin_amdgcn_wave_barrier();
       }
       // Requesters read their new coefficients (a request past the region
-      // reads its sink slot and is redone below).
+      // reads its sink slot and is redone below); a wave without requests
+      // skips the slot checks.
+      if (nreq > 0u) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        if (c[i] != oc[i]) {
-          const int4 v = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(s_req) + kb[i]);
-          a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
-                             __int_as_float(v.w));
+        for (int i = 0; i < P; ++i) {
+          if (c[i] != oc[i]) {
+            const int4 v = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(s_req) + kb[i]);
+            a[i] = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
+                               __int_as_float(v.w));
+          }
         }
+        __builtin_amdgcn_wave_barrier();
       }
-      __builtin_amdgcn_wave_barrier();
       // Rare: more requests than the region holds (a burst of cell changes).
       // Those past it regenerate their window on their own lane.
       if (nreq > (uint32_t)RQ) {
