@@ -341,6 +341,12 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
         }
       }
 
+      // Wave priorities (s_setprio): a wave takes its steps and posts its
+      // requests at the highest priority, serves and reads them back at the
+      // lowest, and publishes its edges towards the barrier in between.  The
+      // SIMD then issues the long, independent step chains first and fills
+      // their gaps with the latency-bound request path of the other waves.
+      __builtin_amdgcn_s_setprio(3);
       // Euler step of every site (Jacobi: old values of the neighbours); a
       // site that changed cell posts a request into this wave's region, at
       // byte offset kb[i] of s_req.  Requests past the region's RQ entries go
@@ -387,6 +393,7 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       // q.  The requests, their node windows and the replies belong to this
       // wave only, and a wave's LDS operations complete in program order, so
       // no workgroup barrier is needed between posting, serving and reading.
+      __builtin_amdgcn_s_setprio(0);
       const uint32_t nserve = nreq < (uint32_t)RQ ? nreq : (uint32_t)RQ;
       if (nserve > 0u) {
         __builtin_amdgcn_wave_barrier();
@@ -455,6 +462,7 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
           }
         }
       }
+      __builtin_amdgcn_s_setprio(2);
       // Publish this wave's end sites for the neighbouring waves' next sub-step.
       if (lane == 0) s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
       if (lane == 63) s_edge[par ^ 1][wv][1] = make_float2(c[P - 1], r[P - 1]);
