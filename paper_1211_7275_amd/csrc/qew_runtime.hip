@@ -49,7 +49,7 @@ constexpr int64_t kMaxL = int64_t(1) << 30;
 constexpr int kGraphLaunches = 16;
 constexpr int64_t kSqChunk = 4096;  // modes per binning chunk
 constexpr int kTuneTiles[5] = {1024, 1536, 2048, 3072, 4096};
-constexpr int kTuneK[4] = {16, 32, 48, 64};
+constexpr int kTuneK[5] = {16, 32, 48, 56, 64};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
