@@ -178,8 +178,8 @@ def test_ensemble_on_device(qew, c0_oracle):
 
 # -------------------------------------------- fused == one-step (bitwise) --
 
-GEOMS = [(1, 1024), (5, 1024), (8, 1024), (13, 1536), (32, 1536), (16, 2048), (32, 2048), (7, 3072),
-         (64, 3072), (32, 4096), (64, 4096)]
+GEOMS = [(1, 1024), (5, 1024), (8, 1024), (13, 1536), (32, 1536), (16, 2048), (32, 2048), (48, 2048),
+         (56, 2048), (7, 3072), (64, 3072), (32, 4096), (64, 4096)]
 SIZES = [3, 5, 31, 64, 100, 511, 1000, 1024, 1500, 5000]
 
 
@@ -370,7 +370,7 @@ def test_zero_disorder_flat_line(qew):
     # requests overflow the per-wave region, on every tile width
     for prec, path, k, tile in [(qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 0, 0),
                                 (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 16, 1024),
-                                (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 64, 2048),
+                                (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 56, 2048),
                                 (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 64, 3072),
                                 (qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP, 0, 0)]:
         say("flat line, strength 0", prec, path, k, tile)
