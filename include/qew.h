@@ -73,6 +73,18 @@ typedef int32_t qew_status;
 /* qew_problem.flags */
 #define QEW_FLAG_NO_GRAPH 1   /* launch every kernel directly instead of replaying hipGraphs */
 #define QEW_FLAG_TIMING   2   /* record hipEvents around the stepping kernels (qew_run_stats) */
+/*
+ * The fused path has two variants of its kernel with identical results: the
+ * dense one posts the cell changes of every sub-step slot by slot; the sparse
+ * one first checks whether any site of a wave changed cell and skips the
+ * bookkeeping when none did (faster for pinned or slow lines, slower for
+ * moving ones).  qew_run starts dense and, before each stretch of steps
+ * between two measurements, picks the variant from the velocities of the
+ * measurement before last (a line at velocity v changes cell about v dt times
+ * per site and step).  These flags force one variant.
+ */
+#define QEW_FLAG_FUSED_DENSE  4
+#define QEW_FLAG_FUSED_SPARSE 8
 
 /*
  * One batch of independent samples sharing c, dt, disorder kind/strength,
@@ -134,6 +146,7 @@ typedef struct qew_run_stats {
   int64_t meas_launches;   /* measurement points taken                                 */
   int64_t site_updates;    /* sum_s L_s * (Euler steps advanced)                       */
   int64_t graph_launches;  /* hipGraphLaunch calls                                     */
+  int64_t sparse_launches; /* fused launches of the sparse variant (counted always)    */
 } qew_run_stats;
 
 /*

@@ -57,8 +57,10 @@ hipError_t launch_step_plain(const Tables& t, const double* uin, double* uout, c
                              int kind, hipStream_t st);
 hipError_t launch_step_split1(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
                               hipStream_t st);
+// `sparse`: the variant that skips the request bookkeeping of a wave whose
+// sites did not change cell (for pinned or slow lines).
 hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
-                             int tile, int halo, int nsub, int grid, hipStream_t st);
+                             int tile, int halo, int nsub, int grid, bool sparse, hipStream_t st);
 int fused_max_grid(int tile);
 bool fused_fits(int tile);  // static LDS of the tile's kernel within the device limit
 hipError_t launch_meas_plain(const Tables& t, const double* u, const Phys& ph, int kind,

@@ -221,7 +221,7 @@ constexpr int kReqPerWave = 64;
 // Waves per SIMD the register allocation must allow (LDS allows the same).
 constexpr int fused_min_waves(int P) { return P == 6 ? 5 : (P <= 8 ? 4 : (P == 12 ? 3 : 2)); }
 
-template <int KIND, int P>
+template <int KIND, int P, bool SPARSE>
 __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
     k_step_fused(Tables t, SplitBuf in, SplitBuf out, Phys ph, int halo, int nsub) {
   constexpr int T = kBlock * P;
@@ -373,6 +373,16 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
         oc[i] = c[i];
         c[i] = oc[i] + split_advance(r[i], F, dt);
       }
+      // The sparse variant first checks whether any site of the wave changed
+      // cell and skips the request bookkeeping when none did.
+      bool book = true;
+      if constexpr (SPARSE) {
+        uint64_t any_move = 0u;
+#pragma unroll
+        for (int i = 0; i < P; ++i) any_move |= __ballot(c[i] != oc[i]);
+        book = any_move != 0u;
+      }
+      if (book) {
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const bool mv = c[i] != oc[i];
@@ -462,6 +472,7 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
           }
         }
       }
+      }  // book
       __builtin_amdgcn_s_setprio(2);
       // Publish this wave's end sites for the neighbouring waves' next sub-step.
       if (lane == 0) s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
@@ -767,7 +778,7 @@ hipError_t launch_step_split1(const Tables& t, SplitBuf in, SplitBuf out, const 
 
 template <int KIND, int P>
 static const void* fused_ptr() {
-  return reinterpret_cast<const void*>(&k_step_fused<KIND, P>);
+  return reinterpret_cast<const void*>(&k_step_fused<KIND, P, false>);
 }
 
 static const void* fused_fn(int tile) {
@@ -801,25 +812,32 @@ bool fused_fits(int tile) {
   return (int)attr.sharedSizeBytes <= max_lds;
 }
 
-template <int KIND>
+template <int KIND, bool SPARSE>
 static void launch_fused_kind(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int tile,
                               int halo, int nsub, dim3 g, dim3 b, hipStream_t st) {
-  if (tile == 1024) hipLaunchKernelGGL((k_step_fused<KIND, 4>), g, b, 0, st, t, in, out, ph, halo, nsub);
-  else if (tile == 1536) hipLaunchKernelGGL((k_step_fused<KIND, 6>), g, b, 0, st, t, in, out, ph, halo, nsub);
-  else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<KIND, 8>), g, b, 0, st, t, in, out, ph, halo, nsub);
-  else if (tile == 3072) hipLaunchKernelGGL((k_step_fused<KIND, 12>), g, b, 0, st, t, in, out, ph, halo, nsub);
-  else hipLaunchKernelGGL((k_step_fused<KIND, 16>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  if (tile == 1024) hipLaunchKernelGGL((k_step_fused<KIND, 4, SPARSE>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else if (tile == 1536) hipLaunchKernelGGL((k_step_fused<KIND, 6, SPARSE>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else if (tile == 2048) hipLaunchKernelGGL((k_step_fused<KIND, 8, SPARSE>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else if (tile == 3072) hipLaunchKernelGGL((k_step_fused<KIND, 12, SPARSE>), g, b, 0, st, t, in, out, ph, halo, nsub);
+  else hipLaunchKernelGGL((k_step_fused<KIND, 16, SPARSE>), g, b, 0, st, t, in, out, ph, halo, nsub);
+}
+
+template <bool SPARSE>
+static void launch_fused_variant(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
+                                 int tile, int halo, int nsub, dim3 g, dim3 b, hipStream_t st) {
+  switch (kind) {
+    case kRF: launch_fused_kind<kRF, SPARSE>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
+    case kRB: launch_fused_kind<kRB, SPARSE>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
+    case kRBLin: launch_fused_kind<kRBLin, SPARSE>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
+    default: launch_fused_kind<kRFPc, SPARSE>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
+  }
 }
 
 hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
-                             int tile, int halo, int nsub, int grid, hipStream_t st) {
+                             int tile, int halo, int nsub, int grid, bool sparse, hipStream_t st) {
   const dim3 g(grid), b(kBlock);
-  switch (kind) {
-    case kRF: launch_fused_kind<kRF>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
-    case kRB: launch_fused_kind<kRB>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
-    case kRBLin: launch_fused_kind<kRBLin>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
-    default: launch_fused_kind<kRFPc>(t, in, out, ph, tile, halo, nsub, g, b, st); break;
-  }
+  if (sparse) launch_fused_variant<true>(t, in, out, ph, kind, tile, halo, nsub, g, b, st);
+  else launch_fused_variant<false>(t, in, out, ph, kind, tile, halo, nsub, g, b, st);
   return hipGetLastError();
 }
 

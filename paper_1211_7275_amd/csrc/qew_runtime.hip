@@ -50,6 +50,10 @@ constexpr int kGraphLaunches = 16;
 constexpr int64_t kSqChunk = 4096;  // modes per binning chunk
 constexpr int kTuneTiles[5] = {1024, 1536, 2048, 3072, 4096};
 constexpr int kTuneK[5] = {16, 32, 48, 56, 64};
+// The fused path switches to its sparse variant when the cell changes expected
+// per wave and sub-step (a wave holds 64 P sites) fall below this: most
+// sub-steps of a wave then have no cell change at all.
+constexpr double kSparseRequestsPerWave = 0.5;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -64,7 +68,7 @@ struct Layout {
 struct GraphCache {
   hipGraphExec_t exec = nullptr;
   void* ws = nullptr;
-  int key_k = -1, key_tile = -1, key_grid = -1;
+  int key_k = -1, key_tile = -1, key_grid = -1, key_sparse = -1;
 };
 
 }  // namespace
@@ -99,6 +103,13 @@ struct qew_plan_s {
   hipStream_t cap_stream = nullptr;
   GraphCache graph;
   qew_run_stats stats{};
+  // fused variant: sparse (1) or dense (0), chosen from the velocities of the
+  // measurement before last (two readback slots used in turn)
+  int sparse = 0;
+  int rb_next = 0;                              // slot of the next readback
+  bool rb_valid[2] = {false, false};            // the slot holds a readback not yet used
+  double* rb_host = nullptr;                    // [2][S] pinned: v of every sample
+  hipEvent_t rb_event[2] = {nullptr, nullptr};  // complete when the slot holds its velocities
 };
 
 namespace {
@@ -316,7 +327,7 @@ hipError_t step_launch(const qew_plan_t* p, void* ws, int from, int nsub, hipStr
   if (!fused(p))
     return launch_step_split1(t, split_buf(p, ws, from), split_buf(p, ws, from ^ 1), ph, p->kind, st);
   return launch_step_fused(t, split_buf(p, ws, from), split_buf(p, ws, from ^ 1), ph, p->kind, p->tile,
-                           p->k, nsub, p->fused_grid, st);
+                           p->k, nsub, p->fused_grid, p->sparse != 0, st);
 }
 
 qew_status ensure_fused_grid(qew_plan_t* p) {
@@ -337,7 +348,8 @@ void drop_graph(qew_plan_t* p) {
 // Graph of kGraphLaunches full launches starting (and ending) at buffer 0.
 qew_status ensure_graph(qew_plan_t* p, void* ws) {
   GraphCache& g = p->graph;
-  if (g.exec && g.ws == ws && g.key_k == p->k && g.key_tile == p->tile && g.key_grid == p->fused_grid)
+  if (g.exec && g.ws == ws && g.key_k == p->k && g.key_tile == p->tile && g.key_grid == p->fused_grid &&
+      g.key_sparse == p->sparse)
     return QEW_OK;
   drop_graph(p);
   if (!p->cap_stream) QEW_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
@@ -361,6 +373,7 @@ qew_status ensure_graph(qew_plan_t* p, void* ws) {
   g.key_k = p->k;
   g.key_tile = p->tile;
   g.key_grid = p->fused_grid;
+  g.key_sparse = p->sparse;
   return QEW_OK;
 }
 
@@ -383,6 +396,7 @@ qew_status advance(qew_plan_t* p, void* ws, int64_t n, hipStream_t st) {
       QEW_HIP(hipGraphLaunch(p->graph.exec, st));
       blocks -= kGraphLaunches;
       p->stats.step_launches += kGraphLaunches;
+      if (p->sparse) p->stats.sparse_launches += kGraphLaunches;
       p->stats.graph_launches++;
     }
   }
@@ -390,12 +404,49 @@ qew_status advance(qew_plan_t* p, void* ws, int64_t n, hipStream_t st) {
     QEW_HIP(step_launch(p, ws, p->cur_buf, kk, st));
     p->cur_buf ^= 1;
     p->stats.step_launches++;
+    if (fused(p) && p->sparse) p->stats.sparse_launches++;
   }
   if (rem) {
     QEW_HIP(step_launch(p, ws, p->cur_buf, rem, st));
     p->cur_buf ^= 1;
     p->stats.step_launches++;
+    if (fused(p) && p->sparse) p->stats.sparse_launches++;
   }
+  return QEW_OK;
+}
+
+// Fused variant for the next stretch of steps (the steps between two
+// measurements), from the velocities of the measurement before last: a line
+// advancing at v changes cell about v dt times per site and step.  The host
+// waits for those velocities, which the device produced while the last
+// stretch was still queued behind them, so the wait leaves no gap on the
+// device.  A flag can force either variant.
+qew_status choose_variant(qew_plan_t* p) {
+  if (p->flags & QEW_FLAG_FUSED_DENSE) { p->sparse = 0; return QEW_OK; }
+  if (p->flags & QEW_FLAG_FUSED_SPARSE) { p->sparse = 1; return QEW_OK; }
+  const int slot = p->rb_next;
+  if (!p->rb_valid[slot]) return QEW_OK;
+  QEW_HIP(hipEventSynchronize(p->rb_event[slot]));
+  p->rb_valid[slot] = false;
+  const double* v = p->rb_host + (size_t)slot * p->S;
+  double moves = 0.0;  // expected cell changes per step over all sites
+  for (int s = 0; s < p->S; ++s) moves += (double)p->L[s] * std::fabs(v[s]) * p->dt;
+  const double per_wave = moves / (double)std::max<int64_t>(p->total_sites, 1) * (p->tile / 4);
+  p->sparse = (std::isfinite(per_wave) && per_wave < kSparseRequestsPerWave) ? 1 : 0;
+  return QEW_OK;
+}
+
+// After measurement mi: send the velocities of every sample to the host
+// (next slot).
+qew_status post_velocities(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
+  const int slot = p->rb_next;
+  const size_t n_meas = p->meas.size();
+  const double* v = reinterpret_cast<const double*>(static_cast<char*>(ws) + p->lay.series) + (size_t)mi * 3;
+  QEW_HIP(hipMemcpy2DAsync(p->rb_host + (size_t)slot * p->S, sizeof(double), v, n_meas * 3 * sizeof(double),
+                           sizeof(double), (size_t)p->S, hipMemcpyDeviceToHost, st));
+  QEW_HIP(hipEventRecord(p->rb_event[slot], st));
+  p->rb_valid[slot] = true;
+  p->rb_next ^= 1;
   return QEW_OK;
 }
 
@@ -473,7 +524,10 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
       pr->tile != 4096)
     return fail(QEW_EINVAL, "tile must be 0, 1024, 1536, 2048, 3072 or 4096");
   if (pr->k > 0 && pr->tile > 0 && 4 * pr->k > pr->tile) return fail(QEW_EINVAL, "need 4*k <= tile");
-  if (pr->flags & ~(QEW_FLAG_NO_GRAPH | QEW_FLAG_TIMING)) return fail(QEW_EINVAL, "unknown flag bits");
+  if (pr->flags & ~(QEW_FLAG_NO_GRAPH | QEW_FLAG_TIMING | QEW_FLAG_FUSED_DENSE | QEW_FLAG_FUSED_SPARSE))
+    return fail(QEW_EINVAL, "unknown flag bits");
+  if ((pr->flags & QEW_FLAG_FUSED_DENSE) && (pr->flags & QEW_FLAG_FUSED_SPARSE))
+    return fail(QEW_EINVAL, "QEW_FLAG_FUSED_DENSE and QEW_FLAG_FUSED_SPARSE exclude each other");
   if (pr->sq_bins < 0) return fail(QEW_EINVAL, "sq_bins must be >= 0");
   if (pr->sq_bins > 0) {
     if (!pr->sq_edges) return fail(QEW_EINVAL, "sq_edges is NULL");
@@ -604,6 +658,7 @@ qew_status qew_autotune(qew_plan_t* p, void* ws, size_t bytes, void* stream) {
   qew_status rc = check_ws(p, ws, bytes);
   if (rc != QEW_OK) return rc;
   if (!fused(p)) return QEW_OK;
+  p->sparse = (p->flags & QEW_FLAG_FUSED_SPARSE) ? 1 : 0;  // time the variant runs start with
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   QEW_HIP(hipEventCreate(&e0));
@@ -662,6 +717,8 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (resume && (p->state_ws != ws)) return fail(QEW_EINVAL, "resume: this workspace holds no state of this plan");
   if (resume && p->cur_step > p->n_steps) return fail(QEW_EINVAL, "resume: state step beyond n_steps");
+  // every run starts dense (or as forced); the variant follows the line from there
+  p->sparse = (p->flags & QEW_FLAG_FUSED_SPARSE) ? 1 : 0;
   if (fused(p) && (p->k_req == 0 || p->tile_req == 0) && !p->autotuned) {
     if (resume) return fail(QEW_EINVAL, "resume: run qew_autotune before writing the state");
     if ((rc = qew_autotune(p, ws, bytes, stream)) != QEW_OK) return rc;
@@ -669,6 +726,15 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   p->stats = qew_run_stats{};
   if ((rc = upload_tables(p, ws, st)) != QEW_OK) return rc;
   QEW_HIP(launch_fill_i32(tables_of(p, ws).err, 1, 0, st));
+  if (fused(p)) {
+    if (!p->rb_host)
+      QEW_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->rb_host), 2 * (size_t)p->S * sizeof(double)));
+    for (int i = 0; i < 2; ++i) {
+      if (!p->rb_event[i]) QEW_HIP(hipEventCreateWithFlags(&p->rb_event[i], hipEventDisableTiming));
+      p->rb_valid[i] = false;
+    }
+    p->rb_next = 0;
+  }
   if ((rc = ensure_fused_grid(p)) != QEW_OK) return rc;
   if (!resume) {
     if ((rc = init_state(p, ws, st)) != QEW_OK) return rc;
@@ -709,6 +775,7 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
       }
       if ((rc = measure(p, ws, mi, st)) != QEW_OK) break;
       if (timing && (he = hipEventRecord(meas_ev.back().b, st)) != hipSuccess) break;
+      if (fused(p) && (rc = post_velocities(p, ws, mi, st)) != QEW_OK) break;
       ++mi;
     }
     if (m >= p->n_steps) break;
@@ -718,6 +785,7 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
       if ((he = mk(step_ev.back())) != hipSuccess) break;
       if ((he = hipEventRecord(step_ev.back().a, st)) != hipSuccess) break;
     }
+    if (fused(p) && (rc = choose_variant(p)) != QEW_OK) break;
     if ((rc = advance(p, ws, stop - m, st)) != QEW_OK) break;
     if (timing && (he = hipEventRecord(step_ev.back().b, st)) != hipSuccess) break;
     m = stop;
@@ -906,6 +974,12 @@ void qew_plan_destroy(qew_plan_t* p) {
   if (!p) return;
   drop_graph(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (hipEvent_t e : p->rb_event) {
+    if (!e) continue;
+    (void)hipEventSynchronize(e);
+    (void)hipEventDestroy(e);
+  }
+  if (p->rb_host) (void)hipHostFree(p->rb_host);
   delete p;
 }
 

@@ -31,6 +31,8 @@ QEW_ONE_STEP = 0
 QEW_FUSED = 1
 QEW_FLAG_NO_GRAPH = 1
 QEW_FLAG_TIMING = 2
+QEW_FLAG_FUSED_DENSE = 4
+QEW_FLAG_FUSED_SPARSE = 8
 
 EXPORTS = ("qew_plan", "qew_workspace_bytes", "qew_plan_info_get", "qew_autotune", "qew_run",
            "qew_ensemble", "qew_sq_get", "qew_run_stats_get", "qew_read_state", "qew_write_state",
@@ -67,6 +69,7 @@ class qew_run_stats(ctypes.Structure):
         ("total_ms", ctypes.c_double), ("step_ms", ctypes.c_double), ("meas_ms", ctypes.c_double),
         ("step_launches", ctypes.c_int64), ("meas_launches", ctypes.c_int64),
         ("site_updates", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
+        ("sparse_launches", ctypes.c_int64),
     ]
 
 

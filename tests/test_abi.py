@@ -89,6 +89,9 @@ def test_plan_rejects_bad_path_options():
     assert _plan_status(p, k=130, tile=4096)[0] == qew.QEW_EINVAL
     assert _plan_status(p, flags=64)[0] == qew.QEW_EINVAL
     assert _plan_status(p, precision=5)[0] == qew.QEW_EINVAL
+    assert _plan_status(p, flags=qew.QEW_FLAG_FUSED_DENSE)[0] == 0
+    assert _plan_status(p, flags=qew.QEW_FLAG_FUSED_SPARSE)[0] == 0
+    assert _plan_status(p, flags=qew.QEW_FLAG_FUSED_DENSE | qew.QEW_FLAG_FUSED_SPARSE)[0] == qew.QEW_EINVAL
 
 
 def test_plan_null_arguments():

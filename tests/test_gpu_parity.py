@@ -198,6 +198,51 @@ def test_fused_bit_identical_to_one_step(qew, kind, period):
             assert np.array_equal(out[key], ref[key]), (k, tile, key)
 
 
+SPARSE_GEOMS = [(5, 1024), (13, 1536), (56, 2048), (64, 3072), (32, 4096)]
+
+
+@pytest.mark.parametrize("kind,period", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 5)])
+def test_fused_sparse_variant_bit_identical(qew, kind, period):
+    """The sparse variant of the fused kernel (forced) gives the one-step states bit for bit."""
+    p = workloads.custom(kind, SIZES, np.linspace(0.6, 1.4, len(SIZES)), 300,
+                         [0, 1, 2, 7, 33, 150, 299, 300], SEED + 5, period=period)
+    ref = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP)
+    for k, tile in SPARSE_GEOMS:
+        say("fused sparse k", k, "tile", tile, "kind", kind)
+        out = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=k, tile=tile, flags=qew.QEW_FLAG_FUSED_SPARSE)
+        for s in range(len(SIZES)):
+            assert np.array_equal(out["u"][s], ref["u"][s]), (k, tile, SIZES[s])
+        for key in ("v", "ubar", "w2"):
+            assert np.array_equal(out[key], ref[key]), (k, tile, key)
+
+
+def test_fused_variant_switch_on_a_pinned_line(qew):
+    """Lines below the threshold pin: qew_run switches to the sparse variant
+    between measurements, and the result stays the one-step result bit for bit."""
+    n = 6000
+    p = workloads.custom(1, [1 << 14] * 4, [0.3, 0.5, 0.7, 0.9], n, workloads.log_steps(n, 30), SEED + 21)
+    ref = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP)
+    runs = {}
+    for name, flags in (("auto", 0), ("dense", qew.QEW_FLAG_FUSED_DENSE)):
+        sim = qew.Simulation(p, precision=qew.QEW_FP32_SPLIT, path=qew.QEW_FUSED, k=32, tile=2048, flags=flags)
+        try:
+            out = sim.run()
+            out["u"] = [sim.read_state(s)[0] for s in range(4)]
+            out["stats"] = sim.stats()
+        finally:
+            sim.close()
+        runs[name] = out
+        say("variant run", name, "sparse launches", out["stats"].sparse_launches, "of",
+            out["stats"].step_launches)
+    assert runs["auto"]["stats"].sparse_launches > 0
+    assert runs["dense"]["stats"].sparse_launches == 0
+    for out in runs.values():
+        for s in range(4):
+            assert np.array_equal(out["u"][s], ref["u"][s])
+        for key in ("v", "ubar", "w2"):
+            assert np.array_equal(out[key], ref[key])
+
+
 def test_graph_replay_matches_direct_launches(qew):
     p = workloads.custom(0, [4096, 3000, 70000], 1.0, 2500, workloads.log_steps(2500, 20), SEED + 6)
     for prec, path, k, tile in [(qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 8, 1024),
