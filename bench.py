@@ -127,16 +127,16 @@ def bench_problem(steps, L=1 << 22, samples=4):
     return p
 
 
-def time_path(qew, p, precision, path, warm_steps, k=0, tile=0):
+def time_path(qew, p, precision, path, warm_steps, k=0, tile=0, flags=0):
     import torch
 
     pw = dict(p, n_steps=int(warm_steps), meas_steps=p["meas_steps"][p["meas_steps"] <= warm_steps])
-    warm = qew.Simulation(pw, precision=precision, path=path, k=k, tile=tile)
+    warm = qew.Simulation(pw, precision=precision, path=path, k=k, tile=tile, flags=flags)
     warm.run()
     info = warm.info()
     warm.close()
     sim = qew.Simulation(p, precision=precision, path=path, k=info.k if path else 0,
-                         tile=info.tile if path else 0, flags=qew.QEW_FLAG_TIMING)
+                         tile=info.tile if path else 0, flags=qew.QEW_FLAG_TIMING | flags)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = sim.run()
@@ -362,8 +362,10 @@ def other_workload(qew, args):
     desc, build = OTHER_WORKLOADS[args.workload]
     steps = args.steps
     p = build(steps)
+    variant = {"auto": 0, "dense": qew.QEW_FLAG_FUSED_DENSE,
+               "sparse": qew.QEW_FLAG_FUSED_SPARSE}[args.fused_variant]
     out, st, info, wall = time_path(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, args.warmup,
-                                    k=args.k, tile=args.tile)
+                                    k=args.k, tile=args.tile, flags=variant)
     value = info.total_sites * steps / wall
     roof = fused_roofline(p["kind"], st, info, out, steps)
     roof["traffic"] = None  # the committed traffic summary covers the benchmark workload only
@@ -373,8 +375,9 @@ def other_workload(qew, args):
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"{args.workload}: {desc}", "samples": len(p["L"]),
                        "total_sites": int(info.total_sites),
-                       "measurements": int(len(p["meas_steps"])), "k": info.k, "tile": info.tile},
-            "roofline": roof,
+                       "measurements": int(len(p["meas_steps"])), "k": info.k, "tile": info.tile,
+                       "fused_variant": args.fused_variant},
+            "roofline": roof, "sparse_launches": int(st.sparse_launches),
             "meas_ms_per_measurement": round(st.meas_ms / max(st.meas_launches, 1), 4),
             "v_last_mean": float(np.nanmean(out["v"][:, -1])) if out["v"].shape[1] else None}
 
@@ -391,6 +394,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--fused-variant", default="auto", choices=("auto", "dense", "sparse"),
+                    help="other workloads: the fused kernel variant (auto: chosen from the "
+                         "measured velocities before each stretch between measurements)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--summarize-profile", metavar="DIR",
