@@ -108,7 +108,7 @@ typedef struct qew_problem {
   int32_t         n_meas;       /* >= 0                                                 */
   int32_t         precision;    /* QEW_FP64_PLAIN or QEW_FP32_SPLIT                     */
   int32_t         path;         /* QEW_ONE_STEP, or QEW_FUSED (FP32 split only)         */
-  int32_t         k;            /* fused: steps per launch, 1..64 (0 = autotune)        */
+  int32_t         k;            /* fused: steps per launch, 1..128 (0 = autotune)       */
   int32_t         tile;         /* fused: sites per workgroup tile, 1024/1536/2048/3072/4096 (0 = autotune); 4k <= tile */
   int32_t         flags;        /* QEW_FLAG_* bits                                      */
   int32_t         period;       /* transverse period M of the disorder in u (node n is

@@ -45,7 +45,7 @@ struct Partial {
 
 constexpr int kMeasTile = 4096;   // sites per measurement / one-step tile
 constexpr int kBlock = 256;       // threads per workgroup of every kernel
-constexpr int kMaxHalo = 64;
+constexpr int kMaxHalo = 128;
 
 // Launchers (return the launch error; all asynchronous on `st`).
 hipError_t launch_init_plain(const Tables& t, double* u, hipStream_t st);

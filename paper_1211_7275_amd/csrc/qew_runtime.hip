@@ -49,7 +49,7 @@ constexpr int64_t kMaxL = int64_t(1) << 30;
 constexpr int kGraphLaunches = 16;
 constexpr int64_t kSqChunk = 4096;  // modes per binning chunk
 constexpr int kTuneTiles[5] = {1024, 1536, 2048, 3072, 4096};
-constexpr int kTuneK[5] = {16, 32, 48, 56, 64};
+constexpr int kTuneK[6] = {16, 32, 48, 56, 64, 96};
 // The fused path switches to its sparse variant when the cell changes expected
 // per wave and sub-step (a wave holds 64 P sites) fall below this: most
 // sub-steps of a wave then have no cell change at all.

@@ -82,9 +82,10 @@ def test_plan_rejects_bad_problems(mutate, expect):
 def test_plan_rejects_bad_path_options():
     p = _base()
     assert _plan_status(p, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_FUSED)[0] == qew.QEW_EUNSUPPORTED
-    assert _plan_status(p, k=65)[0] == qew.QEW_EINVAL
+    assert _plan_status(p, k=129)[0] == qew.QEW_EINVAL
     assert _plan_status(p, tile=700)[0] == qew.QEW_EINVAL
     assert _plan_status(p, k=64, tile=1024)[0] == 0
+    assert _plan_status(p, k=128, tile=2048)[0] == 0
     assert _plan_status(p, tile=512)[0] == qew.QEW_EINVAL
     assert _plan_status(p, k=130, tile=4096)[0] == qew.QEW_EINVAL
     assert _plan_status(p, flags=64)[0] == qew.QEW_EINVAL

@@ -179,7 +179,7 @@ def test_ensemble_on_device(qew, c0_oracle):
 # -------------------------------------------- fused == one-step (bitwise) --
 
 GEOMS = [(1, 1024), (5, 1024), (8, 1024), (13, 1536), (32, 1536), (16, 2048), (32, 2048), (48, 2048),
-         (56, 2048), (7, 3072), (64, 3072), (32, 4096), (64, 4096)]
+         (56, 2048), (128, 2048), (7, 3072), (64, 3072), (96, 3072), (32, 4096), (64, 4096), (128, 4096)]
 SIZES = [3, 5, 31, 64, 100, 511, 1000, 1024, 1500, 5000]
 
 
@@ -198,7 +198,7 @@ def test_fused_bit_identical_to_one_step(qew, kind, period):
             assert np.array_equal(out[key], ref[key]), (k, tile, key)
 
 
-SPARSE_GEOMS = [(5, 1024), (13, 1536), (56, 2048), (64, 3072), (32, 4096)]
+SPARSE_GEOMS = [(5, 1024), (13, 1536), (56, 2048), (64, 3072), (96, 3072), (32, 4096)]
 
 
 @pytest.mark.parametrize("kind,period", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 5)])
@@ -417,6 +417,7 @@ def test_zero_disorder_flat_line(qew):
                                 (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 16, 1024),
                                 (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 56, 2048),
                                 (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 64, 3072),
+                                (qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 128, 4096),
                                 (qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP, 0, 0)]:
         say("flat line, strength 0", prec, path, k, tile)
         out = run_gpu(qew, p, prec, path, k=k, tile=tile)
