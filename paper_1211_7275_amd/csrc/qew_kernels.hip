@@ -199,8 +199,8 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
 //   1. every site takes one Euler step (neighbours within a thread directly,
 //      across lanes by DPP wave shifts, across waves through a double-buffered
 //      LDS edge array);
-//   2. a site whose cell changed posts a request (its LDS node index, new
-//      cell, old cell) into its wave's region of the request list;
+//   2. a site whose cell changed posts a request (its LDS node index and its
+//      new and old cells) into its wave's region of the request list;
 //   3. the same wave serves its requests, lane q taking request q: shift the
 //      node window, generate the missing node (all four after a jump of two
 //      or more cells), store the window, and write the new coefficients into
@@ -394,8 +394,13 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
                         (uint32_t)uniform_i32((int)(rbase_b + nreq * (uint32_t)sizeof(int4))),
                     sink_b);
         if (mv) {
+          // The two cells go in the order of their registers, which swap
+          // roles every sub-step: {new, old} on even sub-steps, {old, new}
+          // on odd ones, so the three words stay one store without copies.
+          const float w1 = par ? oc[i] : c[i];
+          const float w2 = par ? c[i] : oc[i];
           *reinterpret_cast<int3*>(reinterpret_cast<char*>(s_req) + kb[i]) =
-              make_int3(i * kBlock + tid, __float_as_int(c[i]), __float_as_int(oc[i]));
+              make_int3(i * kBlock + tid, __float_as_int(w1), __float_as_int(w2));
         }
         nreq += cnt;
       }
@@ -409,10 +414,10 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
         __builtin_amdgcn_wave_barrier();
         if ((uint32_t)lane < nserve) {
           const int slot = rbase + lane;
-          const int4 rq = s_req[slot];  // {node index, new cell, old cell} (cells relative to cbase)
+          const int4 rq = s_req[slot];  // {node index, cells (relative to cbase) in sub-step order}
           const int ni = rq.x;
-          const float cnew = __int_as_float(rq.y);
-          const float move = cnew - __int_as_float(rq.z);
+          const float cnew = __int_as_float(par ? rq.z : rq.y);
+          const float move = cnew - __int_as_float(par ? rq.y : rq.z);
           const int32_t cell = cbase + (int32_t)cnew;
           const int lp = (int)(((uint32_t)ni % kBlock) * P + (uint32_t)ni / kBlock);  // tile-local position
           int j = start_mod + lp;
