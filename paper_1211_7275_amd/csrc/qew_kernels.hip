@@ -47,6 +47,9 @@ __device__ __forceinline__ float from_upper_lane(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true));
 }
 
+// A pointer into LDS (32-bit, address space 3).
+typedef __attribute__((address_space(3))) float lds_f32;
+
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -229,7 +232,12 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
   constexpr int RQ = kReqPerWave;
   __shared__ float4 s_nodes[T];
   __shared__ int4 s_req[NW * (RQ + 1)];  // per wave: RQ requests, then one sink slot
-  __shared__ float2 s_edge[2][NW][2];
+  // End sites of each wave, double-buffered: [parity][cell, offset][slot][end],
+  // wave w in slot w + 1.  A wave reaches its own and its neighbours' entries
+  // through one LDS pointer held in a vector register, so every access is an
+  // immediate offset of it (no per-access address moves); cells and offsets
+  // are stored as single words, so no two registers need to be adjacent.
+  __shared__ float s_edge[2][2][NW + 2][2];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -242,6 +250,12 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
   asm volatile("" : "+v"(cel));
   asm volatile("" : "+v"(dt));
   const float g = ph.sgn_strf;
+  lds_f32* eb = (lds_f32*)&s_edge[0][0][wv][0];  // slot wv: the left neighbour's entries
+  asm volatile("" : "+v"(eb));
+  // entry of parity `pa`, word q (0 cell, 1 offset), slot wv + ds, end e
+  auto edge = [&](int pa, int q, int ds, int e) -> lds_f32& {
+    return eb[((pa * 2 + q) * (NW + 2) + ds) * 2 + e];
+  };
 
   for (int ti = blockIdx.x; ti < t.n_ft; ti += gridDim.x) {
     const int s = uniform_i32(t.ft_s[ti]);
@@ -308,8 +322,14 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       }
     }
     if (__ballot(far) && lane == 0) atomicOr(t.err, 1);
-    if (lane == 0) s_edge[0][wv][0] = make_float2(c[0], r[0]);
-    if (lane == 63) s_edge[0][wv][1] = make_float2(c[P - 1], r[P - 1]);
+    if (lane == 0) {
+      edge(0, 0, 1, 0) = c[0];
+      edge(0, 1, 1, 0) = r[0];
+    }
+    if (lane == 63) {
+      edge(0, 0, 1, 1) = c[P - 1];
+      edge(0, 1, 1, 1) = r[P - 1];
+    }
     __syncthreads();
 
     // One sub-step; the loop runs it twice per trip so that the state
@@ -322,9 +342,8 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       float rre = from_upper_lane(r[0]);
       if (lane == 0) {
         if (wv > 0) {
-          const float2 e = s_edge[par][wv - 1][1];
-          cle = e.x;
-          rle = e.y;
+          cle = edge(par, 0, 0, 1);
+          rle = edge(par, 1, 0, 1);
         } else {
           cle = c[0];
           rle = r[0];
@@ -332,9 +351,8 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       }
       if (lane == 63) {
         if (wv < NW - 1) {
-          const float2 e = s_edge[par][wv + 1][0];
-          cre = e.x;
-          rre = e.y;
+          cre = edge(par, 0, 2, 0);
+          rre = edge(par, 1, 2, 0);
         } else {
           cre = c[P - 1];
           rre = r[P - 1];
@@ -480,8 +498,14 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
       }  // book
       __builtin_amdgcn_s_setprio(2);
       // Publish this wave's end sites for the neighbouring waves' next sub-step.
-      if (lane == 0) s_edge[par ^ 1][wv][0] = make_float2(c[0], r[0]);
-      if (lane == 63) s_edge[par ^ 1][wv][1] = make_float2(c[P - 1], r[P - 1]);
+      if (lane == 0) {
+        edge(par ^ 1, 0, 1, 0) = c[0];
+        edge(par ^ 1, 1, 1, 0) = r[0];
+      }
+      if (lane == 63) {
+        edge(par ^ 1, 0, 1, 1) = c[P - 1];
+        edge(par ^ 1, 1, 1, 1) = r[P - 1];
+      }
       __syncthreads();
     };
     int sub = 0;
