@@ -528,6 +528,36 @@ def test_full_size_l2e22_sampled_sites(qew, oracle):
     assert np.max(np.abs(d - 0.05 * out["v"][:, :-1])) <= 1e-6
 
 
+def test_full_size_l2e22_benchmark_launches(qew, oracle):
+    """L = 2^22 x 4 in the benchmark's launch configuration (k = 56 steps per
+    launch on 2048-site tiles, the geometry the autotuner picks there): two
+    full launches and a partial one, sampled sites (tile edges, halo borders,
+    chain ends) against the oracle's light-cone windows."""
+    k, tile, N = 56, 2048, 2 * 56 + 19
+    p = workloads.config3(n_steps=N, n_meas=2)
+    p["meas_steps"] = np.array([0, k, 2 * k, N])
+    L = int(p["L"][0])
+    V = tile - 2 * k
+    say("full size L=2^22 x 4, fused k", k, "tile", tile, "steps", N)
+    sim = qew.Simulation(p, precision=qew.QEW_FP32_SPLIT, path=qew.QEW_FUSED, k=k, tile=tile)
+    try:
+        out = sim.run()
+        assert sim.info().k == k and sim.info().tile == tile
+        rng = np.random.default_rng(5)
+        for s in (1, 2):
+            u, step = sim.read_state(s)
+            assert step == N
+            picks = {0, 1, k, L - 1, L - 2, V - 1, V, V + 1, 2 * V - 1, 2 * V, L - V, L // 2 + 7} | \
+                set(int(x) for x in rng.integers(0, L, 12))
+            for jj in sorted(picks):
+                ref = oracle.site_after(0, 1.0, p["seed"], s, L, jj, 1.0, 0.05, 1.0, N)
+                assert abs(u[jj] - ref) <= 1e-4, (s, jj)
+    finally:
+        sim.close()
+    # the line advances (f = 1 is above the threshold) and v stays finite
+    assert np.all(np.isfinite(out["v"])) and np.all(np.diff(out["ubar"], axis=1) > 0.0)
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 def test_full_size_l2e25_sampled_sites(qew, oracle, kind):
     """L = 2^25 x 5 drives around the threshold, one shared disorder (the
