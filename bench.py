@@ -258,10 +258,12 @@ def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
             if not idx:
                 continue
             seg = [r for r in trace[idx[-1]:] if tag in r["Kernel_Name"]]
-            if seg:
-                d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in seg]
-                lines.append(f"\ntimed run: `{short(seg[0]['Kernel_Name'])}` {len(seg)} launches, "
-                             f"average {sum(d) / len(d):.5f} ms")
+            by_name = {}  # each kernel (e.g. each variant of the fused kernel) on its own line
+            for r in seg:
+                by_name.setdefault(short(r["Kernel_Name"]), []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+            for name, d in by_name.items():
+                lines.append(f"\ntimed run: `{name}` {len(d)} launches, average {sum(d) / len(d):.5f} ms")
     counters = rows("*counter_collection.csv")
     if counters:
         # one record per dispatch: name, duration, counter sums
@@ -279,14 +281,16 @@ def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
             inits = [i for i in order if init in disp[i]["name"]]
             if not inits:
                 continue
-            seg = [disp[i] for i in order if i > inits[-1] and tag in disp[i]["name"]]
-            if not seg:
-                continue
-            ms = sum(d["ns"] for d in seg) / 1e6
-            for cn in sorted(seg[0]["c"]):
-                v = [d["c"].get(cn, 0.0) for d in seg]
-                lines.append(f"| `{seg[0]['name']}` | {cn} | {len(v)} | {statistics.median(v):.6g} "
-                             f"| {sum(v):.6g} | {ms:.3f} |")
+            groups = {}
+            for i in order:
+                if i > inits[-1] and tag in disp[i]["name"]:
+                    groups.setdefault(disp[i]["name"], []).append(disp[i])
+            for name, seg in groups.items():
+                ms = sum(d["ns"] for d in seg) / 1e6
+                for cn in sorted(seg[0]["c"]):
+                    v = [d["c"].get(cn, 0.0) for d in seg]
+                    lines.append(f"| `{name}` | {cn} | {len(v)} | {statistics.median(v):.6g} "
+                                 f"| {sum(v):.6g} | {ms:.3f} |")
         copies = [d for d in disp.values() if "copyBuffer" in d["name"]]
         if copies:
             for cn in sorted(copies[0]["c"]):
