@@ -34,7 +34,7 @@ CLOCK_HZ = 2.4e9
 VALU_LANE_OPS = CUS * 4 * 32 * CLOCK_HZ
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic VALU operations of one FP32 split site update (see DESIGN.md):
+# Algorithmic VALU operations of one FP32 split site update:
 # Laplacian on (cell, offset) 7, Catmull-Rom from the four cached nodes 12,
 # total force 2, Euler 1, renormalisation 7.
 OPS_SITE_UPDATE_RF = 29
@@ -419,8 +419,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                                   "run with --gpus 1 (multi-GPU sharding is not built)"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; "
+                                   "run with --gpus 1 (multi-GPU sharding is not implemented)"}))
         sys.exit(2)
 
     import torch
