@@ -388,6 +388,7 @@ qew_status advance(qew_plan_t* p, void* ws, int64_t n, hipStream_t st) {
       QEW_HIP(step_launch(p, ws, p->cur_buf, kk, st));
       p->cur_buf ^= 1;
       p->stats.step_launches++;
+      if (fused(p) && p->sparse) p->stats.sparse_launches++;
       --blocks;
     }
     qew_status rc = ensure_graph(p, ws);

@@ -44,6 +44,7 @@ def run_gpu(qew, p, precision, path, k=0, tile=0, flags=0, states=True):
         if states:
             out["u"] = [sim.read_state(s)[0] for s in range(len(p["L"]))]
         out["info"] = sim.info()
+        out["stats"] = sim.stats()
         return out
     finally:
         sim.close()
@@ -552,10 +553,20 @@ def test_full_size_l2e22_benchmark_launches(qew, oracle):
             for jj in sorted(picks):
                 ref = oracle.site_after(0, 1.0, p["seed"], s, L, jj, 1.0, 0.05, 1.0, N)
                 assert abs(u[jj] - ref) <= 1e-4, (s, jj)
+        dense = [sim.read_state(s)[0] for s in range(4)]
     finally:
         sim.close()
     # the line advances (f = 1 is above the threshold) and v stays finite
     assert np.all(np.isfinite(out["v"])) and np.all(np.diff(out["ubar"], axis=1) > 0.0)
+    # the sparse variant at the same size and geometry gives the same bits
+    say("  the same with the sparse variant forced")
+    sp = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=k, tile=tile,
+                 flags=qew.QEW_FLAG_FUSED_SPARSE)
+    assert sp["stats"].sparse_launches == sp["stats"].step_launches > 0
+    for s in range(4):
+        assert np.array_equal(sp["u"][s], dense[s]), s
+    for key in ("v", "ubar", "w2"):
+        assert np.array_equal(sp[key], out[key]), key
 
 
 @pytest.mark.parametrize("kind", [0, 1])
