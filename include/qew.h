@@ -74,6 +74,9 @@ typedef int32_t qew_status;
 #define QEW_FLAG_NO_GRAPH 1   /* launch every kernel directly instead of replaying hipGraphs */
 #define QEW_FLAG_TIMING   2   /* record hipEvents around the stepping kernels (qew_run_stats) */
 /*
+ * The fused path runs stretches between measurements that are shorter than
+ * four steps with the one-step kernel (same arithmetic, same results).
+ *
  * The fused path has two variants of its kernel with identical results: the
  * dense one posts the cell changes of every sub-step slot by slot; the sparse
  * one first checks whether any site of a wave changed cell and skips the
@@ -81,7 +84,8 @@ typedef int32_t qew_status;
  * moving ones).  qew_run starts dense and, before each stretch of steps
  * between two measurements, picks the variant from the velocities of the
  * measurement before last (a line at velocity v changes cell about v dt times
- * per site and step).  These flags force one variant.
+ * per site and step).  These flags force one variant; they are rejected
+ * (QEW_EINVAL) on the one-step path.
  */
 #define QEW_FLAG_FUSED_DENSE  4
 #define QEW_FLAG_FUSED_SPARSE 8
@@ -137,16 +141,26 @@ typedef struct qew_plan_info {
   int64_t cur_step;      /* step index of the state in the workspace     */
 } qew_plan_info;
 
-/* Timings of the last qew_run with QEW_FLAG_TIMING (HIP events on `stream`). */
+/*
+ * Statistics of the last qew_run.  The durations need QEW_FLAG_TIMING (HIP
+ * events on `stream`); the counts are kept always.  A measurement that rides
+ * on the first step of a stretch (one-step launches) adds that launch to the
+ * stepping time and its per-sample combine to the measurement time.
+ */
 typedef struct qew_run_stats {
   double  total_ms;        /* the whole qew_run on the stream                          */
-  double  step_ms;         /* summed duration of the stepping-kernel segments          */
+  double  step_ms;         /* summed duration of the stepping segments (all kernels)   */
   double  meas_ms;         /* summed duration of the measurement kernels               */
   int64_t step_launches;   /* stepping-kernel launches (graph nodes included)          */
   int64_t meas_launches;   /* measurement points taken                                 */
   int64_t site_updates;    /* sum_s L_s * (Euler steps advanced)                       */
   int64_t graph_launches;  /* hipGraphLaunch calls                                     */
-  int64_t sparse_launches; /* fused launches of the sparse variant (counted always)    */
+  int64_t sparse_launches; /* fused launches of the sparse variant                     */
+  double  fused_ms;        /* summed duration of the segments made of fused launches   */
+  int64_t fused_launches;  /* fused-kernel launches                                    */
+  int64_t fused_steps;     /* Euler steps advanced by fused launches                   */
+  int64_t node_refreshes;  /* rebuilds of the fused path's node cache (after one-step
+                              stretches or a written state)                            */
 } qew_run_stats;
 
 /*

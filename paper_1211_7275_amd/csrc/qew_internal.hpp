@@ -53,10 +53,13 @@ hipError_t launch_init_split(const Tables& t, SplitBuf b, const Phys& ph, int ki
                              hipStream_t st);
 hipError_t launch_refresh_nodes(const Tables& t, SplitBuf b, const Phys& ph, int kind,
                                 hipStream_t st);
+// One Euler step of every site; with `part` non-null the same launch also
+// writes the measurement partials of the input state (the partials
+// launch_meas_* would write, bit for bit).
 hipError_t launch_step_plain(const Tables& t, const double* uin, double* uout, const Phys& ph,
-                             int kind, hipStream_t st);
+                             int kind, Partial* part, hipStream_t st);
 hipError_t launch_step_split1(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
-                              hipStream_t st);
+                              Partial* part, hipStream_t st);
 // `sparse`: the variant that skips the request bookkeeping of a wave whose
 // sites did not change cell (for pinned or slow lines).
 hipError_t launch_step_fused(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
@@ -65,6 +68,9 @@ int fused_max_grid(int tile);
 bool fused_fits(int tile);  // static LDS of the tile's kernel within the device limit
 hipError_t launch_meas_plain(const Tables& t, const double* u, const Phys& ph, int kind,
                              Partial* part, hipStream_t st);
+// Split state: b.nodes non-null means it holds the four nodes of every
+// site's current cell (the fused path's cache), which are then read instead
+// of regenerated.
 hipError_t launch_meas_split(const Tables& t, SplitBuf b, const Phys& ph, int kind, Partial* part,
                              hipStream_t st);
 hipError_t launch_meas_final(const Tables& t, int n_samples, const Partial* part, int meas_index,

@@ -124,9 +124,14 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 // One-step kernels (one Euler step per launch).
 // ---------------------------------------------------------------------------
-template <int KIND>
+// MEAS: also write the measurement partial of the input state (the same
+// loop, forces and reduction order as k_meas_plain, so the partials are the
+// same bits), so a measured step reads the state once.
+template <int KIND, bool MEAS>
 __global__ void __launch_bounds__(kBlock)
-    k_step_plain(Tables t, const double* __restrict__ uin, double* __restrict__ uout, Phys ph) {
+    k_step_plain(Tables t, const double* __restrict__ uin, double* __restrict__ uout, Phys ph,
+                 Partial* part) {
+  __shared__ double lds[MEAS ? 3 * (kBlock / 64) : 1];
   const int tile = blockIdx.x;
   const int s = t.mt_s[tile];
   const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
@@ -136,6 +141,8 @@ __global__ void __launch_bounds__(kBlock)
   const double f = t.f[s];
   const PlainPhys pp{ph.c, ph.dt, ph.strength};
   const VectorKeys keys = vector_keys(ph.k0, ph.k1);
+  const double K = MEAS ? uin[base + p0] : 0.0;
+  double sf = 0.0, s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
     const int jm = (j == 0) ? L - 1 : j - 1;
@@ -144,6 +151,16 @@ __global__ void __launch_bounds__(kBlock)
     const double F = plain_force<KIND>(uin[base + jm], u, uin[base + jp], (uint32_t)j, id, keys, f,
                                        ph.period, pp);
     uout[base + j] = u + ph.dt * F;
+    if constexpr (MEAS) {
+      sf += F;
+      const double x = u - K;
+      s1 += x;
+      s2 += x * x;
+    }
+  }
+  if constexpr (MEAS) {
+    block_sum3(sf, s1, s2, lds);
+    if (threadIdx.x == 0) part[tile] = Partial{sf, s1, s2, K};
   }
 }
 
@@ -162,8 +179,12 @@ __device__ __forceinline__ void nodes_of(uint32_t j, int32_t c, uint32_t id, con
   p3 = cubic ? node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period) : 0.0f;
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, SplitBuf out, Phys ph) {
+// MEAS: also write the measurement partial of the input state, as
+// k_meas_split computes it (same loop, forces and reduction order).
+template <int KIND, bool MEAS>
+__global__ void __launch_bounds__(kBlock)
+    k_step_split1(Tables t, SplitBuf in, SplitBuf out, Phys ph, Partial* part) {
+  __shared__ double lds[MEAS ? 3 * (kBlock / 64) : 1];
   const int tile = blockIdx.x;
   const int s = t.mt_s[tile];
   const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
@@ -172,6 +193,9 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
   const uint32_t id = t.did[s];
   const float f = t.f32[s];
   const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
+  const int32_t Kc = MEAS ? in.cell[base + p0] : 0;
+  const double Kr = MEAS ? (double)in.frac[base + p0] : 0.0;
+  double sf = 0.0, s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
     const int jm = (j == 0) ? L - 1 : j - 1;
@@ -183,9 +207,19 @@ __global__ void __launch_bounds__(kBlock) k_step_split1(Tables t, SplitBuf in, S
     const float4 a = spline_coef<KIND>(n0, n1, n2, n3, sp.sgn_str, f);
     const float F = split_force<KIND>(c, r, in.cell[base + jm], in.frac[base + jm],
                                       in.cell[base + jp], in.frac[base + jp], a, sp.c);
+    if constexpr (MEAS) {
+      sf += (double)F;
+      const double x = (double)(c - Kc) + ((double)r - Kr);  // exact
+      s1 += x;
+      s2 += x * x;
+    }
     c += (int32_t)split_advance(r, F, sp.dt);
     out.cell[base + j] = c;
     out.frac[base + j] = r;
+  }
+  if constexpr (MEAS) {
+    block_sum3(sf, s1, s2, lds);
+    if (threadIdx.x == 0) part[tile] = Partial{sf, s1, s2, (double)Kc + Kr};
   }
 }
 
@@ -606,7 +640,15 @@ __global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phy
     const int32_t c = b.cell[base + j];
     const float r = b.frac[base + j];
     float n0, n1, n2, n3;
-    nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+    if (b.nodes) {  // the node cache of the fused path holds the same four values
+      const float4 nd = b.nodes[base + j];
+      n0 = nd.x;
+      n1 = nd.y;
+      n2 = nd.z;
+      n3 = nd.w;
+    } else {
+      nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+    }
     const float4 a = spline_coef<KIND>(n0, n1, n2, n3, sp.sgn_str, f);
     const float F = split_force<KIND>(c, r, b.cell[base + jm], b.frac[base + jm], b.cell[base + jp],
                                       b.frac[base + jp], a, sp.c);
@@ -793,15 +835,39 @@ hipError_t launch_refresh_nodes(const Tables& t, SplitBuf b, const Phys& ph, int
   return hipGetLastError();
 }
 
+template <int KIND>
+static void launch_plain_kind(const Tables& t, const double* uin, double* uout, const Phys& ph,
+                              Partial* part, hipStream_t st) {
+  if (part) hipLaunchKernelGGL((k_step_plain<KIND, true>), dim3(t.n_mt), dim3(kBlock), 0, st, t, uin, uout, ph, part);
+  else hipLaunchKernelGGL((k_step_plain<KIND, false>), dim3(t.n_mt), dim3(kBlock), 0, st, t, uin, uout, ph, part);
+}
+
 hipError_t launch_step_plain(const Tables& t, const double* uin, double* uout, const Phys& ph,
-                             int kind, hipStream_t st) {
-  QEW_KIND_DISPATCH(kind, k_step_plain, dim3(t.n_mt), dim3(kBlock), 0, st, t, uin, uout, ph);
+                             int kind, Partial* part, hipStream_t st) {
+  switch (kind) {
+    case kRF: launch_plain_kind<kRF>(t, uin, uout, ph, part, st); break;
+    case kRB: launch_plain_kind<kRB>(t, uin, uout, ph, part, st); break;
+    case kRBLin: launch_plain_kind<kRBLin>(t, uin, uout, ph, part, st); break;
+    default: launch_plain_kind<kRFPc>(t, uin, uout, ph, part, st); break;
+  }
   return hipGetLastError();
 }
 
+template <int KIND>
+static void launch_split1_kind(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph,
+                               Partial* part, hipStream_t st) {
+  if (part) hipLaunchKernelGGL((k_step_split1<KIND, true>), dim3(t.n_mt), dim3(kBlock), 0, st, t, in, out, ph, part);
+  else hipLaunchKernelGGL((k_step_split1<KIND, false>), dim3(t.n_mt), dim3(kBlock), 0, st, t, in, out, ph, part);
+}
+
 hipError_t launch_step_split1(const Tables& t, SplitBuf in, SplitBuf out, const Phys& ph, int kind,
-                              hipStream_t st) {
-  QEW_KIND_DISPATCH(kind, k_step_split1, dim3(t.n_mt), dim3(kBlock), 0, st, t, in, out, ph);
+                              Partial* part, hipStream_t st) {
+  switch (kind) {
+    case kRF: launch_split1_kind<kRF>(t, in, out, ph, part, st); break;
+    case kRB: launch_split1_kind<kRB>(t, in, out, ph, part, st); break;
+    case kRBLin: launch_split1_kind<kRBLin>(t, in, out, ph, part, st); break;
+    default: launch_split1_kind<kRFPc>(t, in, out, ph, part, st); break;
+  }
   return hipGetLastError();
 }
 

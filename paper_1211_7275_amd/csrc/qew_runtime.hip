@@ -50,6 +50,12 @@ constexpr int kGraphLaunches = 16;
 constexpr int64_t kSqChunk = 4096;  // modes per binning chunk
 constexpr int kTuneTiles[5] = {1024, 1536, 2048, 3072, 4096};
 constexpr int kTuneK[6] = {16, 32, 48, 56, 64, 96};
+// The fused path runs stretches shorter than this with the one-step kernel:
+// a fused launch moves the state and its node cache through HBM (48 B per
+// site) however few steps it takes, while a one-step launch moves 16 B per
+// site and its first step also takes the measurement the stretch starts
+// with.  The node cache is rebuilt before the next fused launch.
+constexpr int64_t kShortStretch = 4;
 // The fused path switches to its sparse variant when the cell changes expected
 // per wave and sub-step (a wave holds 64 P sites) fall below this: most
 // sub-steps of a wave then have no cell change at all.
@@ -65,10 +71,15 @@ struct Layout {
   size_t total;
 };
 
+// A captured sequence of kGraphLaunches stepping launches.  A plan keeps one
+// per kernel variant (fused: dense and sparse; one-step: slot 0), so a
+// variant switch inside a run never destroys a graph that may still be
+// queued.  An entry is replaced only when its workspace or geometry changed,
+// which happens between runs, after qew_run has drained its stream.
 struct GraphCache {
   hipGraphExec_t exec = nullptr;
   void* ws = nullptr;
-  int key_k = -1, key_tile = -1, key_grid = -1, key_sparse = -1;
+  int key_k = -1, key_tile = -1, key_grid = -1;
 };
 
 }  // namespace
@@ -101,7 +112,7 @@ struct qew_plan_s {
   bool nodes_valid = false;
   int fused_grid = 0;
   hipStream_t cap_stream = nullptr;
-  GraphCache graph;
+  GraphCache graph[2];
   qew_run_stats stats{};
   // fused variant: sparse (1) or dense (0), chosen from the velocities of the
   // measurement before last (two readback slots used in turn)
@@ -318,16 +329,33 @@ qew_status init_state(qew_plan_t* p, void* ws, hipStream_t st) {
   return QEW_OK;
 }
 
-// One launch of the stepping kernel: nsub Euler steps from buffer `from`.
-hipError_t step_launch(const qew_plan_t* p, void* ws, int from, int nsub, hipStream_t st) {
+Partial* partials_of(const qew_plan_t* p, void* ws) {
+  return reinterpret_cast<Partial*>(static_cast<char*>(ws) + p->lay.part);
+}
+
+// One Euler step from buffer `from` with the one-step kernel of the plan's
+// precision (the split one-step kernel on the fused path); with `part`
+// non-null it also writes the measurement partials of the state it reads.
+hipError_t onestep_launch(const qew_plan_t* p, void* ws, int from, Partial* part, hipStream_t st) {
   const Tables t = tables_of(p, ws);
   const Phys ph = phys_of(p);
   if (p->precision == QEW_FP64_PLAIN)
-    return launch_step_plain(t, plain_buf(p, ws, from), plain_buf(p, ws, from ^ 1), ph, p->kind, st);
-  if (!fused(p))
-    return launch_step_split1(t, split_buf(p, ws, from), split_buf(p, ws, from ^ 1), ph, p->kind, st);
-  return launch_step_fused(t, split_buf(p, ws, from), split_buf(p, ws, from ^ 1), ph, p->kind, p->tile,
-                           p->k, nsub, p->fused_grid, p->sparse != 0, st);
+    return launch_step_plain(t, plain_buf(p, ws, from), plain_buf(p, ws, from ^ 1), ph, p->kind, part, st);
+  SplitBuf in = split_buf(p, ws, from), out = split_buf(p, ws, from ^ 1);
+  in.nodes = out.nodes = nullptr;  // the one-step kernel regenerates nodes
+  return launch_step_split1(t, in, out, ph, p->kind, part, st);
+}
+
+// One launch of the fused kernel: nsub Euler steps from buffer `from`.
+hipError_t fused_launch(const qew_plan_t* p, void* ws, int from, int nsub, hipStream_t st) {
+  return launch_step_fused(tables_of(p, ws), split_buf(p, ws, from), split_buf(p, ws, from ^ 1), phys_of(p),
+                           p->kind, p->tile, p->k, nsub, p->fused_grid, p->sparse != 0, st);
+}
+
+// The plan's stepping launch: fused (nsub steps) on the fused path, else one step.
+hipError_t step_launch(const qew_plan_t* p, void* ws, int from, int nsub, hipStream_t st) {
+  if (fused(p)) return fused_launch(p, ws, from, nsub, st);
+  return onestep_launch(p, ws, from, nullptr, st);
 }
 
 qew_status ensure_fused_grid(qew_plan_t* p) {
@@ -340,18 +368,24 @@ qew_status ensure_fused_grid(qew_plan_t* p) {
   return QEW_OK;
 }
 
-void drop_graph(qew_plan_t* p) {
-  if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
-  p->graph = GraphCache{};
+void drop_graph(GraphCache& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g = GraphCache{};
 }
 
-// Graph of kGraphLaunches full launches starting (and ending) at buffer 0.
+// Only between runs (the stream of the last run has drained; qew_run
+// synchronizes its stream before it returns, on success and on failure).
+void drop_graphs(qew_plan_t* p) {
+  for (GraphCache& g : p->graph) drop_graph(g);
+}
+
+// Graph of kGraphLaunches full launches of the current variant starting
+// (and ending) at buffer 0.
 qew_status ensure_graph(qew_plan_t* p, void* ws) {
-  GraphCache& g = p->graph;
-  if (g.exec && g.ws == ws && g.key_k == p->k && g.key_tile == p->tile && g.key_grid == p->fused_grid &&
-      g.key_sparse == p->sparse)
+  GraphCache& g = p->graph[fused(p) && p->sparse ? 1 : 0];
+  if (g.exec && g.ws == ws && g.key_k == p->k && g.key_tile == p->tile && g.key_grid == p->fused_grid)
     return QEW_OK;
-  drop_graph(p);
+  drop_graph(g);
   if (!p->cap_stream) QEW_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   QEW_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
@@ -373,46 +407,66 @@ qew_status ensure_graph(qew_plan_t* p, void* ws) {
   g.key_k = p->k;
   g.key_tile = p->tile;
   g.key_grid = p->fused_grid;
-  g.key_sparse = p->sparse;
   return QEW_OK;
 }
 
-// Advance the state by n Euler steps (buffer parity tracked in the plan).
+void count_launches(qew_plan_t* p, int64_t n, bool fused_kernel) {
+  p->stats.step_launches += n;
+  if (fused_kernel) {
+    p->stats.fused_launches += n;
+    if (p->sparse) p->stats.sparse_launches += n;
+  }
+}
+
+// Advance the state by n Euler steps with the plan's stepping kernel
+// (buffer parity tracked in the plan).
 qew_status advance(qew_plan_t* p, void* ws, int64_t n, hipStream_t st) {
   const int kk = p->k;
   int64_t blocks = n / kk;
   const int rem = (int)(n % kk);
   const bool use_graph = !(p->flags & QEW_FLAG_NO_GRAPH);
+  const bool fk = fused(p);
   if (use_graph && blocks >= kGraphLaunches + (p->cur_buf ? 1 : 0)) {
     if (p->cur_buf) {
       QEW_HIP(step_launch(p, ws, p->cur_buf, kk, st));
       p->cur_buf ^= 1;
-      p->stats.step_launches++;
-      if (fused(p) && p->sparse) p->stats.sparse_launches++;
+      count_launches(p, 1, fk);
       --blocks;
     }
     qew_status rc = ensure_graph(p, ws);
     if (rc != QEW_OK) return rc;
+    const hipGraphExec_t exec = p->graph[fk && p->sparse ? 1 : 0].exec;
     while (blocks >= kGraphLaunches) {
-      QEW_HIP(hipGraphLaunch(p->graph.exec, st));
+      QEW_HIP(hipGraphLaunch(exec, st));
       blocks -= kGraphLaunches;
-      p->stats.step_launches += kGraphLaunches;
-      if (p->sparse) p->stats.sparse_launches += kGraphLaunches;
+      count_launches(p, kGraphLaunches, fk);
       p->stats.graph_launches++;
     }
   }
   for (; blocks > 0; --blocks) {
     QEW_HIP(step_launch(p, ws, p->cur_buf, kk, st));
     p->cur_buf ^= 1;
-    p->stats.step_launches++;
-    if (fused(p) && p->sparse) p->stats.sparse_launches++;
+    count_launches(p, 1, fk);
   }
   if (rem) {
     QEW_HIP(step_launch(p, ws, p->cur_buf, rem, st));
     p->cur_buf ^= 1;
-    p->stats.step_launches++;
-    if (fused(p) && p->sparse) p->stats.sparse_launches++;
+    count_launches(p, 1, fk);
   }
+  if (fk) p->stats.fused_steps += n;
+  return QEW_OK;
+}
+
+// n Euler steps with the one-step kernel on the fused path (short stretches);
+// the first one also writes the measurement partials when `part` is given.
+// The node cache no longer matches the state afterwards.
+qew_status advance_onestep(qew_plan_t* p, void* ws, int64_t n, Partial* part, hipStream_t st) {
+  for (int64_t i = 0; i < n; ++i) {
+    QEW_HIP(onestep_launch(p, ws, p->cur_buf, i == 0 ? part : nullptr, st));
+    p->cur_buf ^= 1;
+    count_launches(p, 1, false);
+  }
+  if (fused(p) && n > 0) p->nodes_valid = false;
   return QEW_OK;
 }
 
@@ -451,21 +505,19 @@ qew_status post_velocities(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
   return QEW_OK;
 }
 
-qew_status measure(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
+// Measurement mi of the state in buffer `buf`, from the tile partials already
+// written (by the measurement kernels or by a one-step launch that also
+// measured): per-sample v, ubar, w2 into the series, and the structure
+// factor when the problem asks for it.
+qew_status measure_finish(qew_plan_t* p, void* ws, int mi, int buf, hipStream_t st) {
   const Tables t = tables_of(p, ws);
-  const Phys ph = phys_of(p);
-  Partial* part = reinterpret_cast<Partial*>(static_cast<char*>(ws) + p->lay.part);
-  double* series = reinterpret_cast<double*>(static_cast<char*>(ws) + p->lay.series);
-  if (p->precision == QEW_FP64_PLAIN)
-    QEW_HIP(launch_meas_plain(t, plain_buf(p, ws, p->cur_buf), ph, p->kind, part, st));
-  else
-    QEW_HIP(launch_meas_split(t, split_buf(p, ws, p->cur_buf), ph, p->kind, part, st));
-  QEW_HIP(launch_meas_final(t, p->S, part, mi, (int)p->meas.size(), series, st));
+  double* series = series_of(p, ws);
+  QEW_HIP(launch_meas_final(t, p->S, partials_of(p, ws), mi, (int)p->meas.size(), series, st));
   if (p->sq_bins > 0) {
     char* b = static_cast<char*>(ws);
     const bool plain = p->precision == QEW_FP64_PLAIN;
-    QEW_HIP(launch_sq(t.off, p->S, p->L[0], plain ? plain_buf(p, ws, p->cur_buf) : nullptr,
-                      plain ? SplitBuf{} : split_buf(p, ws, p->cur_buf),
+    QEW_HIP(launch_sq(t.off, p->S, p->L[0], plain ? plain_buf(p, ws, buf) : nullptr,
+                      plain ? SplitBuf{} : split_buf(p, ws, buf),
                       reinterpret_cast<double2*>(b + p->lay.fftA), reinterpret_cast<double2*>(b + p->lay.fftB),
                       reinterpret_cast<const int32_t*>(b + p->lay.sq_chunk_lo),
                       (int)p->sq_chunk_lo.size() - 1, reinterpret_cast<const int32_t*>(b + p->lay.sq_chunk_first),
@@ -474,6 +526,21 @@ qew_status measure(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
   }
   p->stats.meas_launches++;
   return QEW_OK;
+}
+
+// Measurement mi of the current state by the measurement kernels (the split
+// state's nodes come from the fused path's cache while it is valid).
+qew_status measure(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
+  const Tables t = tables_of(p, ws);
+  const Phys ph = phys_of(p);
+  if (p->precision == QEW_FP64_PLAIN) {
+    QEW_HIP(launch_meas_plain(t, plain_buf(p, ws, p->cur_buf), ph, p->kind, partials_of(p, ws), st));
+  } else {
+    SplitBuf b = split_buf(p, ws, p->cur_buf);
+    if (!(fused(p) && p->nodes_valid)) b.nodes = nullptr;
+    QEW_HIP(launch_meas_split(t, b, ph, p->kind, partials_of(p, ws), st));
+  }
+  return measure_finish(p, ws, mi, p->cur_buf, st);
 }
 
 qew_status check_ws(const qew_plan_t* p, const void* ws, size_t bytes) {
@@ -529,6 +596,8 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
     return fail(QEW_EINVAL, "unknown flag bits");
   if ((pr->flags & QEW_FLAG_FUSED_DENSE) && (pr->flags & QEW_FLAG_FUSED_SPARSE))
     return fail(QEW_EINVAL, "QEW_FLAG_FUSED_DENSE and QEW_FLAG_FUSED_SPARSE exclude each other");
+  if ((pr->flags & (QEW_FLAG_FUSED_DENSE | QEW_FLAG_FUSED_SPARSE)) && pr->path != QEW_FUSED)
+    return fail(QEW_EINVAL, "QEW_FLAG_FUSED_DENSE / QEW_FLAG_FUSED_SPARSE apply to the fused path only");
   if (pr->sq_bins < 0) return fail(QEW_EINVAL, "sq_bins must be >= 0");
   if (pr->sq_bins > 0) {
     if (!pr->sq_edges) return fail(QEW_EINVAL, "sq_edges is NULL");
@@ -706,7 +775,7 @@ qew_status qew_autotune(qew_plan_t* p, void* ws, size_t bytes, void* stream) {
   build_fused_tiles(p, best_tile, best_k);
   p->autotuned = 1;
   p->state_ws = nullptr;  // the state was overwritten
-  drop_graph(p);
+  drop_graphs(p);  // the candidates' launches above have completed (event synchronized)
   return QEW_OK;
 }
 
@@ -739,12 +808,10 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   if ((rc = ensure_fused_grid(p)) != QEW_OK) return rc;
   if (!resume) {
     if ((rc = init_state(p, ws, st)) != QEW_OK) return rc;
-  } else if (fused(p) && !p->nodes_valid) {
-    QEW_HIP(launch_refresh_nodes(tables_of(p, ws), split_buf(p, ws, p->cur_buf), phys_of(p), p->kind, st));
-    p->nodes_valid = true;
   }
   const bool timing = (p->flags & QEW_FLAG_TIMING) != 0;
   std::vector<EventPair> step_ev, meas_ev;
+  std::vector<char> step_fused;  // per stepping segment: made of fused launches
   EventPair whole;
   auto mk = [&](EventPair& e) -> hipError_t {
     hipError_t r = hipEventCreate(&e.a);
@@ -757,6 +824,21 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
     if (whole.a) (void)hipEventDestroy(whole.a);
     if (whole.b) (void)hipEventDestroy(whole.b);
   };
+  // Events around a stepping segment (a stretch's launches of one kind) or a
+  // measurement, when timing.
+  auto open_ev = [&](std::vector<EventPair>& v) -> hipError_t {
+    if (!timing) return hipSuccess;
+    v.emplace_back();
+    hipError_t r = mk(v.back());
+    return r == hipSuccess ? hipEventRecord(v.back().a, st) : r;
+  };
+  auto close_ev = [&](std::vector<EventPair>& v) -> hipError_t {
+    return timing ? hipEventRecord(v.back().b, st) : hipSuccess;
+  };
+  auto open_step = [&](bool fk) -> hipError_t {
+    if (timing) step_fused.push_back(fk ? 1 : 0);
+    return open_ev(step_ev);
+  };
   const int64_t step0 = p->cur_step;
   const int n_meas = (int)p->meas.size();
   int mi = (int)(std::lower_bound(p->meas.begin(), p->meas.end(), step0) - p->meas.begin());
@@ -766,29 +848,65 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
     he = mk(whole);
     if (he == hipSuccess) he = hipEventRecord(whole.a, st);
   }
+  // Walk the stretches between measurement steps.  A stretch that starts at a
+  // measurement and runs on the one-step kernel takes that measurement in its
+  // first launch; otherwise the measurement kernels run first.  On the fused
+  // path, stretches shorter than kShortStretch run on the one-step kernel.
   int64_t m = step0;
   while (he == hipSuccess && rc == QEW_OK) {
-    if (mi < n_meas && p->meas[mi] == m) {
-      if (timing) {
-        meas_ev.emplace_back();
-        if ((he = mk(meas_ev.back())) != hipSuccess) break;
-        if ((he = hipEventRecord(meas_ev.back().a, st)) != hipSuccess) break;
+    const bool meas_here = mi < n_meas && p->meas[mi] == m;
+    if (m >= p->n_steps) {
+      if (meas_here) {
+        if ((he = open_ev(meas_ev)) != hipSuccess) break;
+        if ((rc = measure(p, ws, mi, st)) != QEW_OK) break;
+        if ((he = close_ev(meas_ev)) != hipSuccess) break;
+        ++mi;
       }
-      if ((rc = measure(p, ws, mi, st)) != QEW_OK) break;
-      if (timing && (he = hipEventRecord(meas_ev.back().b, st)) != hipSuccess) break;
+      break;
+    }
+    const int next = mi + (meas_here ? 1 : 0);
+    const int64_t stop = next < n_meas ? p->meas[next] : p->n_steps;
+    int64_t n = stop - m;
+    const bool onestep = !fused(p) || n < kShortStretch;
+    if (meas_here) {
+      if (onestep) {
+        const int from = p->cur_buf;
+        if ((he = open_step(false)) != hipSuccess) break;
+        if ((rc = advance_onestep(p, ws, 1, partials_of(p, ws), st)) != QEW_OK) break;
+        if ((he = close_ev(step_ev)) != hipSuccess) break;
+        if ((he = open_ev(meas_ev)) != hipSuccess) break;
+        if ((rc = measure_finish(p, ws, mi, from, st)) != QEW_OK) break;
+        if ((he = close_ev(meas_ev)) != hipSuccess) break;
+        --n;
+      } else {
+        if ((he = open_ev(meas_ev)) != hipSuccess) break;
+        if ((rc = measure(p, ws, mi, st)) != QEW_OK) break;
+        if ((he = close_ev(meas_ev)) != hipSuccess) break;
+      }
       if (fused(p) && (rc = post_velocities(p, ws, mi, st)) != QEW_OK) break;
       ++mi;
     }
-    if (m >= p->n_steps) break;
-    const int64_t stop = (mi < n_meas) ? p->meas[mi] : p->n_steps;
-    if (timing) {
-      step_ev.emplace_back();
-      if ((he = mk(step_ev.back())) != hipSuccess) break;
-      if ((he = hipEventRecord(step_ev.back().a, st)) != hipSuccess) break;
+    if (n > 0 && onestep) {
+      if ((he = open_step(false)) != hipSuccess) break;
+      if (fused(p)) rc = advance_onestep(p, ws, n, nullptr, st);
+      else rc = advance(p, ws, n, st);
+      if (rc != QEW_OK) break;
+      if ((he = close_ev(step_ev)) != hipSuccess) break;
+    } else if (n > 0) {
+      if (!p->nodes_valid) {  // after one-step stretches or a written state
+        if ((he = open_step(false)) != hipSuccess) break;
+        if ((he = launch_refresh_nodes(tables_of(p, ws), split_buf(p, ws, p->cur_buf), phys_of(p), p->kind,
+                                       st)) != hipSuccess)
+          break;
+        if ((he = close_ev(step_ev)) != hipSuccess) break;
+        p->nodes_valid = true;
+        p->stats.node_refreshes++;
+      }
+      if ((rc = choose_variant(p)) != QEW_OK) break;
+      if ((he = open_step(true)) != hipSuccess) break;
+      if ((rc = advance(p, ws, n, st)) != QEW_OK) break;
+      if ((he = close_ev(step_ev)) != hipSuccess) break;
     }
-    if (fused(p) && (rc = choose_variant(p)) != QEW_OK) break;
-    if ((rc = advance(p, ws, stop - m, st)) != QEW_OK) break;
-    if (timing && (he = hipEventRecord(step_ev.back().b, st)) != hipSuccess) break;
     m = stop;
   }
   if (he == hipSuccess && rc == QEW_OK && timing) he = hipEventRecord(whole.b, st);
@@ -831,8 +949,12 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   }
   if (timing) {
     float ms = 0.0f;
-    for (auto& e : step_ev)
-      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) p->stats.step_ms += ms;
+    for (size_t i = 0; i < step_ev.size(); ++i) {
+      const EventPair& e = step_ev[i];
+      if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
+      p->stats.step_ms += ms;
+      if (step_fused[i]) p->stats.fused_ms += ms;
+    }
     for (auto& e : meas_ev)
       if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) p->stats.meas_ms += ms;
     if (hipEventElapsedTime(&ms, whole.a, whole.b) == hipSuccess) p->stats.total_ms = ms;
@@ -841,7 +963,6 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   p->stats.site_updates = p->total_sites * (p->n_steps - step0);
   p->cur_step = p->n_steps;
   p->state_ws = ws;
-  p->nodes_valid = true;
   return QEW_OK;
 }
 
@@ -973,7 +1094,7 @@ qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, in
 
 void qew_plan_destroy(qew_plan_t* p) {
   if (!p) return;
-  drop_graph(p);
+  drop_graphs(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (hipEvent_t e : p->rb_event) {
     if (!e) continue;

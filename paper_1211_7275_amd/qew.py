@@ -12,8 +12,7 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# QEW_LIB_PATH selects another build of the same library (A/B timing of builds).
-LIB_PATH = os.environ.get("QEW_LIB_PATH") or os.path.join(_HERE, "lib", "libqew.so")
+LIB_PATH = os.path.join(_HERE, "lib", "libqew.so")
 
 QEW_OK = 0
 QEW_EINVAL = -1
@@ -69,7 +68,9 @@ class qew_run_stats(ctypes.Structure):
         ("total_ms", ctypes.c_double), ("step_ms", ctypes.c_double), ("meas_ms", ctypes.c_double),
         ("step_launches", ctypes.c_int64), ("meas_launches", ctypes.c_int64),
         ("site_updates", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
-        ("sparse_launches", ctypes.c_int64),
+        ("sparse_launches", ctypes.c_int64), ("fused_ms", ctypes.c_double),
+        ("fused_launches", ctypes.c_int64), ("fused_steps", ctypes.c_int64),
+        ("node_refreshes", ctypes.c_int64),
     ]
 
 

@@ -93,6 +93,11 @@ def test_plan_rejects_bad_path_options():
     assert _plan_status(p, flags=qew.QEW_FLAG_FUSED_DENSE)[0] == 0
     assert _plan_status(p, flags=qew.QEW_FLAG_FUSED_SPARSE)[0] == 0
     assert _plan_status(p, flags=qew.QEW_FLAG_FUSED_DENSE | qew.QEW_FLAG_FUSED_SPARSE)[0] == qew.QEW_EINVAL
+    # the variant flags belong to the fused path
+    for fl in (qew.QEW_FLAG_FUSED_DENSE, qew.QEW_FLAG_FUSED_SPARSE):
+        for prec in (qew.QEW_FP32_SPLIT, qew.QEW_FP64_PLAIN):
+            st, msg = _plan_status(p, precision=prec, path=qew.QEW_ONE_STEP, flags=fl)
+            assert st == qew.QEW_EINVAL and "fused path only" in msg
 
 
 def test_plan_null_arguments():

@@ -244,6 +244,62 @@ def test_fused_variant_switch_on_a_pinned_line(qew):
             assert np.array_equal(out[key], ref[key])
 
 
+def test_sparse_counts_with_a_stretch_on_buffer_one(qew):
+    """A one-step stretch leaves the state in buffer 1; the next stretch of 17
+    full fused launches then starts with one direct launch and replays the
+    captured graph.  With the sparse variant forced every fused launch is a
+    sparse launch, the one-step launch is not, and the states equal the
+    one-step path's bit for bit."""
+    k, n = 8, 1 + 17 * 8 + 3
+    p = workloads.custom(0, [4096, 3000], 1.0, n, [0, 1, n], SEED + 22)
+    ref = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP)
+    out = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=k, tile=1024, flags=qew.QEW_FLAG_FUSED_SPARSE)
+    st = out["stats"]
+    say("sparse counts: step", st.step_launches, "fused", st.fused_launches, "sparse", st.sparse_launches,
+        "graphs", st.graph_launches, "refreshes", st.node_refreshes)
+    assert st.graph_launches == 1
+    assert st.fused_launches == 17 + 1  # 139 steps: 17 full launches and the 3-step rest
+    assert st.sparse_launches == st.fused_launches == st.step_launches - 1
+    assert st.fused_steps == n - 1 and st.node_refreshes == 1
+    for s in range(2):
+        assert np.array_equal(out["u"][s], ref["u"][s])
+    for key in ("v", "ubar", "w2"):
+        assert np.array_equal(out[key], ref[key])
+
+
+def test_short_stretches_mix_one_step_and_fused_launches(qew):
+    """A measurement at every one of the first 12 steps, then sparser ones:
+    the fused path runs the short stretches with the one-step kernel (each
+    taking its measurement in its first launch), rebuilds its node cache, and
+    continues fused; states and series equal the one-step path's bit for bit
+    (so the fused path's measurements from its node cache equal the one-step
+    path's measured launches)."""
+    n = 400
+    meas = list(range(13)) + [15, 20, 40, 41, 43, 100, 101, 250, 400]
+    p = workloads.custom(1, [5000, 1024, 777], [1.5, 2.5, 3.0], n, meas, SEED + 23)
+    ref = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_ONE_STEP)
+    out = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=16, tile=1024)
+    st = out["stats"]
+    say("short stretches: step", st.step_launches, "fused", st.fused_launches, "refreshes", st.node_refreshes)
+    # one-step stretches: twelve of 1 step, 12..15, 40..41, 41..43, 100..101 (19 steps);
+    # the node cache is rebuilt before the fused stretches at 15, 43 and 101
+    assert st.node_refreshes == 3
+    assert st.fused_steps == n - 19
+    for s in range(3):
+        assert np.array_equal(out["u"][s], ref["u"][s])
+    for key in ("v", "ubar", "w2"):
+        assert np.array_equal(out[key], ref[key])
+    # a measurement riding on the first step of a stretch equals the
+    # measurement kernels' at the end of a run, in both precisions
+    for prec in (qew.QEW_FP64_PLAIN, qew.QEW_FP32_SPLIT):
+        a = run_gpu(qew, dict(p, n_steps=40, meas_steps=np.array([40])), prec, qew.QEW_ONE_STEP,
+                    states=False)
+        b = run_gpu(qew, dict(p, n_steps=41, meas_steps=np.array([40, 41])), prec, qew.QEW_ONE_STEP,
+                    states=False)
+        for key in ("v", "ubar", "w2"):
+            assert np.array_equal(a[key][:, 0], b[key][:, 0])
+
+
 def test_graph_replay_matches_direct_launches(qew):
     p = workloads.custom(0, [4096, 3000, 70000], 1.0, 2500, workloads.log_steps(2500, 20), SEED + 6)
     for prec, path, k, tile in [(qew.QEW_FP32_SPLIT, qew.QEW_FUSED, 8, 1024),
@@ -562,7 +618,7 @@ def test_full_size_l2e22_benchmark_launches(qew, oracle):
     say("  the same with the sparse variant forced")
     sp = run_gpu(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, k=k, tile=tile,
                  flags=qew.QEW_FLAG_FUSED_SPARSE)
-    assert sp["stats"].sparse_launches == sp["stats"].step_launches > 0
+    assert sp["stats"].sparse_launches == sp["stats"].fused_launches == sp["stats"].step_launches > 0
     for s in range(4):
         assert np.array_equal(sp["u"][s], dense[s]), s
     for key in ("v", "ubar", "w2"):

@@ -483,6 +483,32 @@ def test_structure_factor_single_mode(oracle):
     assert S[:-1].max() < 1e-26
 
 
+def test_sq_binned_multi_mode_bins(oracle):
+    """Bins of one, two, five and eight modes (the last one closing at mode L/2):
+    each entry is the mean of S_n over its modes, written out by hand.  Mode n
+    sits at index n - 1, so a slice shifted by one changes every bin."""
+    S = np.arange(1.0, 17.0) ** 2  # S_n = n^2 for n = 1 .. 16 (L = 32)
+    got = oracle.sq_binned(S, [1, 2, 4, 9, 17])
+    want = [1.0, (4.0 + 9.0) / 2, (16.0 + 25.0 + 36.0 + 49.0 + 64.0) / 5,
+            (81.0 + 100.0 + 121.0 + 144.0 + 169.0 + 196.0 + 225.0 + 256.0) / 8]
+    assert np.array_equal(got, want)
+    # bins that do not start at mode 1 and skip modes between them
+    assert np.array_equal(oracle.sq_binned(S, [3, 5, 16]), [(9.0 + 16.0) / 2, sum(n * n for n in range(5, 16)) / 11])
+
+
+def test_sq_binned_of_two_modes(oracle):
+    """u = A cos(2 pi 3 x / L) + B cos(2 pi 5 x / L): S_3 = A^2 / 4 and S_5 =
+    B^2 / 4, so the bins [1, 4) and [4, 9) hold A^2 / 12 and B^2 / 20, and the
+    bin [9, L/2 + 1) holds nothing."""
+    L, A, B = 64, 1.5, 0.5
+    x = np.arange(L)
+    S = oracle.structure_factor(A * np.cos(2 * np.pi * 3 * x / L) + B * np.cos(2 * np.pi * 5 * x / L))
+    got = oracle.sq_binned(S, [1, 4, 9, L // 2 + 1])
+    assert got[0] == pytest.approx(A * A / 12, rel=1e-12)
+    assert got[1] == pytest.approx(B * B / 20, rel=1e-12)
+    assert got[2] < 1e-28
+
+
 def test_structure_factor_of_a_relaxing_mode(oracle):
     """No disorder, start u = A cos(2 pi k x / L): each Euler step multiplies
     the mode by 1 - 4 c dt sin^2(pi k / L), so S_k(m) = A^2 lambda^(2m) / 4
