@@ -199,6 +199,31 @@ qew_status qew_run(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *stream, 
                    double *h_v, double *h_w2, double *h_ubar);
 
 /*
+ * qew_run for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, kernels and results as qew_run, but the call allocates nothing,
+ * on the device or the host.  The chains stay in d_ws (its size and
+ * alignment as for qew_run); the plan's tables, tile lists, measurement
+ * partials and series live in a device scratch array of the library, 8 MiB
+ * per GPU, held from the library's load until the process ends (its address
+ * is looked up once per device, on the first call there).  No autotuning,
+ * graphs, events or pinned readbacks: the fused kernel runs its dense variant
+ * (or the one a flag forces), launched directly; QEW_FLAG_TIMING gives no
+ * durations.  After the call the series are also in d_ws, so qew_ensemble,
+ * qew_read_state and a later qew_run with resume = 1 see this run.
+ * Calls on one GPU share its scratch array: calls that overlap in time on one
+ * GPU (other threads, other streams) race and must not be made.
+ * Errors (before any device work): QEW_EINVAL for a fused plan without a
+ * fixed geometry (give k and tile, or run qew_autotune first);
+ * QEW_EUNSUPPORTED for a plan with structure-factor bins; QEW_ENOMEM when the
+ * plan's tables, partials and series exceed the scratch array (about
+ * 44 B per 4096 sites, 12 B per fused tile and 24 B per sample and
+ * measurement); then as qew_run.
+ */
+qew_status qew_run_noalloc(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *stream, int32_t resume,
+                           double *h_v, double *h_w2, double *h_ubar);
+
+/*
  * Disorder average (the overbar of Sec. II, Eqs. (3)-(5)) of the series held
  * in the workspace, computed on the device in FP64 with equal weight per
  * sample, for every measurement taken so far.  h_out is a host array

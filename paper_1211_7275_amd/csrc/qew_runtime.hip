@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,16 @@
 #include "qew_internal.hpp"
 
 using namespace qew;
+
+// Scratch of qew_run_noalloc: the plan's tables, tile lists, measurement
+// partials and series, for callers that cannot allocate.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel or copy: it uses the device
+// address that hipGetSymbolAddress returns, fetched once per device.  Calls
+// of qew_run_noalloc on one GPU share the array, so calls that overlap on
+// one GPU race (each call rewrites tables, flags and series before use).
+static constexpr size_t kScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -67,7 +78,9 @@ struct Layout {
   size_t err, off, L, f, f32, did, mt_s, mt_p0, mt_len, mt_first, ft_s, ft_p0, ft_len, sq_chunk_lo,
       sq_chunk_first;
   size_t tables_end;
-  size_t part, series, ens, sq_series, sq_part, fftA, fftB, stA0, stA1, stB0, stB1, ndA, ndB;
+  size_t part, series, ens;
+  size_t small_end;  // end of the tables, partials and series (the regions qew_run_noalloc keeps in scratch)
+  size_t sq_series, sq_part, fftA, fftB, stA0, stA1, stB0, stB1, ndA, ndB;
   size_t total;
 };
 
@@ -105,7 +118,10 @@ struct qew_plan_s {
   int32_t ft_capacity = 0;
   int32_t k = 1, tile = 0, autotuned = 0;
   Layout lay{};
+  std::vector<char> table_img;  // host image of the table region (current tile lists)
   // run state
+  char* small_base = nullptr;  // during qew_run_noalloc: base of the small regions (the scratch array)
+  bool direct_only = false;    // during qew_run_noalloc: no graphs, events or host readbacks
   int64_t cur_step = 0;
   int cur_buf = 0;
   void* state_ws = nullptr;
@@ -127,6 +143,8 @@ namespace {
 
 bool fused(const qew_plan_t* p) { return p->path == QEW_FUSED; }
 
+void refresh_table_image(qew_plan_t* p);
+
 void build_fused_tiles(qew_plan_t* p, int tile, int k) {
   p->ft_s.clear();
   p->ft_p0.clear();
@@ -142,6 +160,7 @@ void build_fused_tiles(qew_plan_t* p, int tile, int k) {
   }
   p->k = k;
   p->tile = tile;
+  if (p->lay.total) refresh_table_image(p);
 }
 
 int64_t fused_tile_count(const qew_plan_t* p, int tile, int k) {
@@ -181,6 +200,7 @@ void compute_layout(qew_plan_t* p) {
   l.part = take(nmt * sizeof(Partial));
   l.series = take(S * std::max<size_t>(p->meas.size(), 1) * 3 * 8);
   l.ens = take(7 * std::max<size_t>(p->meas.size(), 1) * 8);
+  l.small_end = o;
   if (p->sq_bins > 0) {
     const size_t half = (size_t)(p->L[0] / 2);
     l.sq_series = take(std::max<size_t>(p->meas.size(), 1) * p->sq_bins * 8);
@@ -211,8 +231,15 @@ void compute_layout(qew_plan_t* p) {
   l.total = o;
 }
 
+// Base of the small regions (tables, partials, series): the workspace, or the
+// scratch array during qew_run_noalloc.  The state buffers are always in the
+// workspace.
+char* small_of(const qew_plan_t* p, void* ws) {
+  return p->small_base ? p->small_base : static_cast<char*>(ws);
+}
+
 Tables tables_of(const qew_plan_t* p, void* ws) {
-  char* b = static_cast<char*>(ws);
+  char* b = small_of(p, ws);
   const Layout& l = p->lay;
   Tables t;
   t.off = reinterpret_cast<const int64_t*>(b + l.off);
@@ -262,10 +289,12 @@ SplitBuf split_buf(const qew_plan_t* p, void* ws, int which) {
   return s;
 }
 
-// Host image of the table region (offsets as laid out in the workspace).
-std::vector<char> table_image(const qew_plan_t* p) {
+// Host image of the table region (offsets as laid out in the workspace), kept
+// in the plan and rebuilt whenever the fused tile list changes.
+void refresh_table_image(qew_plan_t* p) {
   const Layout& l = p->lay;
-  std::vector<char> img(l.tables_end, 0);
+  std::vector<char>& img = p->table_img;
+  img.assign(l.tables_end, 0);
   auto put = [&](size_t at, const void* src, size_t bytes) {
     if (bytes) std::memcpy(img.data() + at, src, bytes);
   };
@@ -289,18 +318,17 @@ std::vector<char> table_image(const qew_plan_t* p) {
   put(l.ft_len, p->ft_len.data(), p->ft_len.size() * 4);
   put(l.sq_chunk_lo, p->sq_chunk_lo.data(), p->sq_chunk_lo.size() * 4);
   put(l.sq_chunk_first, p->sq_chunk_first.data(), p->sq_chunk_first.size() * 4);
-  return img;
 }
 
+// Copy the plan's table image to the small regions' base (no allocation).
 qew_status upload_tables(qew_plan_t* p, void* ws, hipStream_t st) {
-  std::vector<char> img = table_image(p);
-  QEW_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
+  QEW_HIP(hipMemcpyAsync(small_of(p, ws), p->table_img.data(), p->table_img.size(), hipMemcpyHostToDevice, st));
   QEW_HIP(hipStreamSynchronize(st));
   return QEW_OK;
 }
 
 double* series_of(const qew_plan_t* p, void* ws) {
-  return reinterpret_cast<double*>(static_cast<char*>(ws) + p->lay.series);
+  return reinterpret_cast<double*>(small_of(p, ws) + p->lay.series);
 }
 
 // Measurements not yet taken read as NaN.
@@ -330,7 +358,7 @@ qew_status init_state(qew_plan_t* p, void* ws, hipStream_t st) {
 }
 
 Partial* partials_of(const qew_plan_t* p, void* ws) {
-  return reinterpret_cast<Partial*>(static_cast<char*>(ws) + p->lay.part);
+  return reinterpret_cast<Partial*>(small_of(p, ws) + p->lay.part);
 }
 
 // One Euler step from buffer `from` with the one-step kernel of the plan's
@@ -424,7 +452,7 @@ qew_status advance(qew_plan_t* p, void* ws, int64_t n, hipStream_t st) {
   const int kk = p->k;
   int64_t blocks = n / kk;
   const int rem = (int)(n % kk);
-  const bool use_graph = !(p->flags & QEW_FLAG_NO_GRAPH);
+  const bool use_graph = !(p->flags & QEW_FLAG_NO_GRAPH) && !p->direct_only;
   const bool fk = fused(p);
   if (use_graph && blocks >= kGraphLaunches + (p->cur_buf ? 1 : 0)) {
     if (p->cur_buf) {
@@ -496,7 +524,7 @@ qew_status choose_variant(qew_plan_t* p) {
 qew_status post_velocities(qew_plan_t* p, void* ws, int mi, hipStream_t st) {
   const int slot = p->rb_next;
   const size_t n_meas = p->meas.size();
-  const double* v = reinterpret_cast<const double*>(static_cast<char*>(ws) + p->lay.series) + (size_t)mi * 3;
+  const double* v = series_of(p, ws) + (size_t)mi * 3;
   QEW_HIP(hipMemcpy2DAsync(p->rb_host + (size_t)slot * p->S, sizeof(double), v, n_meas * 3 * sizeof(double),
                            sizeof(double), (size_t)p->S, hipMemcpyDeviceToHost, st));
   QEW_HIP(hipEventRecord(p->rb_event[slot], st));
@@ -555,6 +583,30 @@ qew_status check_ws(const qew_plan_t* p, const void* ws, size_t bytes) {
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (fetched with that
+// device current on its first use).
+qew_status scratch_of_current_device(char** out) {
+  int dev = -1;
+  QEW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QEW_EUNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(QEW_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+    if ((reinterpret_cast<uintptr_t>(ptr) & 255u) != 0)
+      return fail(QEW_EDEVICE, "the scratch array is not 256-byte aligned");
+    g_scratch_addr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_addr[dev];
+  return QEW_OK;
+}
 
 }  // namespace
 
@@ -698,6 +750,7 @@ qew_status qew_plan(const qew_problem* pr, qew_plan_t** out) {
     p->tile = 0;
   }
   compute_layout(p);
+  refresh_table_image(p);
   *out = p;
   return QEW_OK;
 }
@@ -779,24 +832,42 @@ qew_status qew_autotune(qew_plan_t* p, void* ws, size_t bytes, void* stream) {
   return QEW_OK;
 }
 
-qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t resume, double* h_v,
-                   double* h_w2, double* h_ubar) {
-  g_err.clear();
+// qew_run and qew_run_noalloc.  `noalloc`: the small regions (tables,
+// partials, series) live in the scratch array at `scratch` and the run makes
+// no allocation of any kind: no autotuning, graphs, events, pinned readbacks
+// or host buffers; the fused kernel runs its dense variant (or the forced
+// one), which gives the same results as the automatic choice.
+static qew_status run_impl(qew_plan_t* p, void* ws, size_t bytes, hipStream_t st, int32_t resume,
+                           double* h_v, double* h_w2, double* h_ubar, char* scratch) {
+  const bool noalloc = scratch != nullptr;
   qew_status rc = check_ws(p, ws, bytes);
   if (rc != QEW_OK) return rc;
-  hipStream_t st = static_cast<hipStream_t>(stream);
   if (resume && (p->state_ws != ws)) return fail(QEW_EINVAL, "resume: this workspace holds no state of this plan");
   if (resume && p->cur_step > p->n_steps) return fail(QEW_EINVAL, "resume: state step beyond n_steps");
   // every run starts dense (or as forced); the variant follows the line from there
   p->sparse = (p->flags & QEW_FLAG_FUSED_SPARSE) ? 1 : 0;
   if (fused(p) && (p->k_req == 0 || p->tile_req == 0) && !p->autotuned) {
     if (resume) return fail(QEW_EINVAL, "resume: run qew_autotune before writing the state");
-    if ((rc = qew_autotune(p, ws, bytes, stream)) != QEW_OK) return rc;
+    if ((rc = qew_autotune(p, ws, bytes, st)) != QEW_OK) return rc;
   }
+  // Small regions in the scratch array for this run only (every exit below
+  // passes through the guard, which restores the workspace as their base).
+  struct SmallBase {
+    qew_plan_t* p;
+    ~SmallBase() {
+      p->small_base = nullptr;
+      p->direct_only = false;
+    }
+  } guard{p};
+  p->small_base = scratch;
+  p->direct_only = noalloc;
   p->stats = qew_run_stats{};
   if ((rc = upload_tables(p, ws, st)) != QEW_OK) return rc;
   QEW_HIP(launch_fill_i32(tables_of(p, ws).err, 1, 0, st));
-  if (fused(p)) {
+  if (noalloc && resume)  // this plan's series so far, from the workspace
+    QEW_HIP(hipMemcpyAsync(series_of(p, ws), static_cast<char*>(ws) + p->lay.series,
+                           (size_t)p->S * p->meas.size() * 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (fused(p) && !noalloc) {
     if (!p->rb_host)
       QEW_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->rb_host), 2 * (size_t)p->S * sizeof(double)));
     for (int i = 0; i < 2; ++i) {
@@ -809,7 +880,7 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   if (!resume) {
     if ((rc = init_state(p, ws, st)) != QEW_OK) return rc;
   }
-  const bool timing = (p->flags & QEW_FLAG_TIMING) != 0;
+  const bool timing = (p->flags & QEW_FLAG_TIMING) != 0 && !noalloc;
   std::vector<EventPair> step_ev, meas_ev;
   std::vector<char> step_fused;  // per stepping segment: made of fused launches
   EventPair whole;
@@ -883,7 +954,7 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
         if ((rc = measure(p, ws, mi, st)) != QEW_OK) break;
         if ((he = close_ev(meas_ev)) != hipSuccess) break;
       }
-      if (fused(p) && (rc = post_velocities(p, ws, mi, st)) != QEW_OK) break;
+      if (fused(p) && !noalloc && (rc = post_velocities(p, ws, mi, st)) != QEW_OK) break;
       ++mi;
     }
     if (n > 0 && onestep) {
@@ -902,7 +973,7 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
         p->nodes_valid = true;
         p->stats.node_refreshes++;
       }
-      if ((rc = choose_variant(p)) != QEW_OK) break;
+      if (!noalloc && (rc = choose_variant(p)) != QEW_OK) break;
       if ((he = open_step(true)) != hipSuccess) break;
       if ((rc = advance(p, ws, n, st)) != QEW_OK) break;
       if ((he = close_ev(step_ev)) != hipSuccess) break;
@@ -919,13 +990,33 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   }
   std::vector<double> series;
   int err_flags = 0;
-  if (n_meas > mi0) {
+  const double* d_series = series_of(p, ws);
+  if (noalloc) {
+    // Each output straight from the device series (rows of {v, ubar, w2} per
+    // sample and measurement), then the series back to the workspace so the
+    // plan's other calls see this run.
+    double* const outs[3] = {h_v, h_ubar, h_w2};
+    for (int q = 0; q < 3 && he == hipSuccess && n_meas > mi0; ++q) {
+      if (!outs[q]) continue;
+      if (mi0 == 0) {
+        he = hipMemcpy2DAsync(outs[q], sizeof(double), d_series + q, 3 * sizeof(double), sizeof(double),
+                              (size_t)p->S * n_meas, hipMemcpyDeviceToHost, st);
+      } else {
+        for (int s = 0; s < p->S && he == hipSuccess; ++s)
+          he = hipMemcpy2DAsync(outs[q] + (size_t)s * n_meas + mi0, sizeof(double),
+                                d_series + ((size_t)s * n_meas + mi0) * 3 + q, 3 * sizeof(double), sizeof(double),
+                                (size_t)(n_meas - mi0), hipMemcpyDeviceToHost, st);
+      }
+    }
+    if (he == hipSuccess && n_meas > 0)
+      he = hipMemcpyAsync(static_cast<char*>(ws) + p->lay.series, d_series, (size_t)p->S * n_meas * 3 * sizeof(double),
+                          hipMemcpyDeviceToDevice, st);
+  } else if (n_meas > mi0) {
     series.resize((size_t)p->S * n_meas * 3);
-    he = hipMemcpyAsync(series.data(), static_cast<char*>(ws) + p->lay.series, series.size() * 8,
-                        hipMemcpyDeviceToHost, st);
+    he = hipMemcpyAsync(series.data(), d_series, series.size() * 8, hipMemcpyDeviceToHost, st);
   }
   if (he == hipSuccess)
-    he = hipMemcpyAsync(&err_flags, static_cast<char*>(ws) + p->lay.err, 4, hipMemcpyDeviceToHost, st);
+    he = hipMemcpyAsync(&err_flags, small_of(p, ws) + p->lay.err, 4, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) {
     cleanup();
@@ -939,7 +1030,7 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
                 "the cells of a fused tile spread over 2^23 or more (state far from a line); "
                 "use the one-step path for this state");
   }
-  for (int s = 0; s < p->S && n_meas > mi0; ++s) {
+  for (int s = 0; s < p->S && n_meas > mi0 && !noalloc; ++s) {
     for (int i = mi0; i < n_meas; ++i) {
       const double* x = &series[((size_t)s * n_meas + i) * 3];
       if (h_v) h_v[(size_t)s * n_meas + i] = x[0];
@@ -964,6 +1055,33 @@ qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t 
   p->cur_step = p->n_steps;
   p->state_ws = ws;
   return QEW_OK;
+}
+
+qew_status qew_run(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t resume, double* h_v,
+                   double* h_w2, double* h_ubar) {
+  g_err.clear();
+  return run_impl(p, ws, bytes, static_cast<hipStream_t>(stream), resume, h_v, h_w2, h_ubar, nullptr);
+}
+
+qew_status qew_run_noalloc(qew_plan_t* p, void* ws, size_t bytes, void* stream, int32_t resume,
+                           double* h_v, double* h_w2, double* h_ubar) {
+  g_err.clear();
+  if (!p) return fail(QEW_EINVAL, "plan is NULL");
+  if (p->sq_bins > 0)
+    return fail(QEW_EUNSUPPORTED, "qew_run_noalloc: the structure factor's FFT buffers are not scratch-sized; "
+                                  "use qew_run");
+  if (fused(p) && (p->k_req == 0 || p->tile_req == 0) && !p->autotuned)
+    return fail(QEW_EINVAL, "qew_run_noalloc needs a fixed fused geometry: give k and tile in the problem, "
+                            "or run qew_autotune first");
+  if (p->lay.small_end > kScratchBytes)
+    return fail(QEW_ENOMEM, "qew_run_noalloc: the plan's tables, partials and series need %zu bytes; the "
+                            "scratch array holds %zu",
+                p->lay.small_end, kScratchBytes);
+  qew_status rc = check_ws(p, ws, bytes);
+  if (rc != QEW_OK) return rc;
+  char* scratch_base = nullptr;
+  if ((rc = scratch_of_current_device(&scratch_base)) != QEW_OK) return rc;
+  return run_impl(p, ws, bytes, static_cast<hipStream_t>(stream), resume, h_v, h_w2, h_ubar, scratch_base);
 }
 
 qew_status qew_ensemble(const qew_plan_t* p, const void* ws, void* stream, double* h_out) {

@@ -34,7 +34,7 @@ QEW_FLAG_FUSED_DENSE = 4
 QEW_FLAG_FUSED_SPARSE = 8
 
 EXPORTS = ("qew_plan", "qew_workspace_bytes", "qew_plan_info_get", "qew_autotune", "qew_run",
-           "qew_ensemble", "qew_sq_get", "qew_run_stats_get", "qew_read_state", "qew_write_state",
+           "qew_run_noalloc", "qew_ensemble", "qew_sq_get", "qew_run_stats_get", "qew_read_state", "qew_write_state",
            "qew_debug_philox_fill", "qew_debug_force_eval", "qew_plan_destroy", "qew_last_error")
 
 ENSEMBLE_ROWS = ("v", "v_se", "w2", "w2_se", "ubar", "ubar_se", "w2_about_ensemble_ubar")
@@ -90,6 +90,8 @@ def _load():
     lib.qew_autotune.restype = st
     lib.qew_run.argtypes = [vp, vp, sz, vp, ctypes.c_int32, dp, dp, dp]
     lib.qew_run.restype = st
+    lib.qew_run_noalloc.argtypes = [vp, vp, sz, vp, ctypes.c_int32, dp, dp, dp]
+    lib.qew_run_noalloc.restype = st
     lib.qew_ensemble.argtypes = [vp, vp, vp, dp]
     lib.qew_ensemble.restype = st
     lib.qew_sq_get.argtypes = [vp, vp, vp, dp]
@@ -162,6 +164,11 @@ def qew_autotune(plan, ws, stream=None):
 def qew_run(plan, ws, stream, resume, h_v, h_w2, h_ubar):
     _check(_lib.qew_run(plan, ws.data_ptr(), ws.numel(), _stream_ptr(stream), int(resume),
                         _dptr(h_v), _dptr(h_w2), _dptr(h_ubar)), "qew_run")
+
+
+def qew_run_noalloc(plan, ws, stream, resume, h_v, h_w2, h_ubar):
+    _check(_lib.qew_run_noalloc(plan, ws.data_ptr(), ws.numel(), _stream_ptr(stream), int(resume),
+                                _dptr(h_v), _dptr(h_w2), _dptr(h_ubar)), "qew_run_noalloc")
 
 
 def qew_ensemble(plan, ws, n_meas, stream=None):

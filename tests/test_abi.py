@@ -175,3 +175,30 @@ def test_plan_structure_factor_options():
         qew.qew_plan_destroy(h)
     # two complex FP64 buffers of L/2 per sample, plus 3 x 513 bins
     assert sizes[1] - sizes[0] >= 2 * 3 * 512 * 16 + 3 * 513 * 8
+
+
+def test_run_noalloc_rejects_before_any_device_work():
+    """qew_run_noalloc refuses, on the host and before touching a device, a
+    fused plan without a fixed geometry, a plan with structure-factor bins,
+    and a plan whose tables, partials and series exceed its 8 MiB scratch."""
+    lib = qew.lib()
+    assert lib.qew_run_noalloc(None, None, 0, None, 0, None, None, None) == qew.QEW_EINVAL
+
+    def status(p, **kw):
+        pr, keep = qew.make_problem(p, **kw)
+        h = ctypes.c_void_p()
+        assert lib.qew_plan(ctypes.byref(pr), ctypes.byref(h)) == 0
+        try:
+            st = lib.qew_run_noalloc(h, None, 0, None, 0, None, None, None)
+            return st, qew.qew_last_error()
+        finally:
+            lib.qew_plan_destroy(h)
+
+    st, msg = status(_base())  # fused, k = tile = 0
+    assert st == qew.QEW_EINVAL and "fixed fused geometry" in msg
+    sq = workloads.custom(0, [64], 1.0, 10, [10], 1, sq_edges=workloads.sq_edges_full(64))
+    st, msg = status(sq, k=8, tile=1024)
+    assert st == qew.QEW_EUNSUPPORTED and "structure factor" in msg
+    big = workloads.custom(0, [64] * 64, 1.0, 6000, np.arange(1, 6001), 1)  # 9.2 MB of series
+    st, msg = status(big, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_ONE_STEP)
+    assert st == qew.QEW_ENOMEM and "scratch array holds 8388608" in msg
