@@ -289,6 +289,45 @@ qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, in
                                 const int32_t *d_cell, const double *d_frac, double *d_out,
                                 int64_t N, void *stream);
 
+/*
+ * Critical force f_c^s and critical configuration u_c^s of samples periodic
+ * in u with period M (Sec. III A): the pinned solution of
+ *   c d2u/dx2 + F_p(u, x) + f = 0                                   (Sec. III A)
+ * with the largest f.  The Middleton theorems make it reachable without
+ * integrating Eq. (1): from a configuration whose forces are all >= 0,
+ * moving a site forward to the first zero of its own force (neighbours held)
+ * keeps every force >= 0 and never passes a pinned configuration ahead, so
+ * such moves climb to the leftmost pinned configuration ahead if there is
+ * one; a line that advances by M at every site has passed none, so there is
+ * none at that drive (the translates of a pinned configuration by M are
+ * pinned too).  Each sample is bisected on f independently: the start d_u is
+ * first relaxed at f_lo (each site moved to the nearest zero of its force in
+ * the force's direction), then each trial drive starts from the last pinned
+ * configuration and is decided pinned when every |force| <= tol_force,
+ * depinned when every site advanced by M.  One workgroup per sample runs the
+ * whole bisection in one launch, with the chain in LDS.
+ *   kind: QEW_RF_CR_UNIFORM or QEW_RB_CR_GAUSS (continuous forces; else
+ *         QEW_EUNSUPPORTED).  Disorder as in qew_problem (Philox counter
+ *         (j, n mod M, disorder id, 0), values times strength).
+ *   n_samples S >= 1, 3 <= L <= 4096, 1 <= period M < 2^30, c > 0,
+ *   f_lo < f_hi finite, tol_f > 0 (at most 200 halvings of f_hi - f_lo),
+ *   tol_force > 0, max_sweeps >= 4 (sweeps per trial before it counts as
+ *   undecided; one sweep moves the even and then the odd sites).
+ *   d_disorder_id: device [S] uint32.
+ *   d_u: device [S][L] FP64, the start on entry (e.g. the flat line), on
+ *        return the last pinned configuration (u_c^s at f_lo when done).
+ *   d_f: device [S][2] FP64 out: the final bracket f_lo <= f_c^s < f_hi,
+ *        f_hi - f_lo < tol_f.
+ *   d_status: device [S][2] int64 out: status (0 done; 1 no pinned
+ *        configuration reached at f_lo; 2 a trial undecided within
+ *        max_sweeps; 3 out of rounds) and the sweeps made.
+ * Asynchronous on `stream`; arguments are checked on the host first.
+ */
+qew_status qew_critical_force(int32_t kind, double strength, uint64_t seed, int32_t period, double c,
+                              int32_t n_samples, int32_t L, const uint32_t *d_disorder_id, double f_lo,
+                              double f_hi, double tol_f, double tol_force, int64_t max_sweeps, double *d_u,
+                              double *d_f, int64_t *d_status, void *stream);
+
 /* Free a plan (NULL is allowed); releases its hipGraphs. */
 void qew_plan_destroy(qew_plan_t *plan);
 

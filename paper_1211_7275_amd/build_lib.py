@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libqew.so")
-SOURCES = [os.path.join(CSRC, n) for n in ("qew_kernels.hip", "qew_sq.hip", "qew_runtime.hip")]
+SOURCES = [os.path.join(CSRC, n) for n in ("qew_kernels.hip", "qew_sq.hip", "qew_critical.hip", "qew_runtime.hip")]
 ARCH = os.environ.get("QEW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

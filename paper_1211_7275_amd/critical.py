@@ -3,21 +3,21 @@
 
 A sample of L columns whose disorder repeats with period M in u (the
 transverse period of the library's disorder) has a largest drive f_c^s at
-which a pinned solution of c d2u/dx2 + F_p(u, x) + f = 0 exists.  Every
-sample of a batch is bisected on f independently, and every trial of a round
-runs in one FP64 batch through the library:
+which a pinned solution of c d2u/dx2 + F_p(u, x) + f = 0 exists.
 
-- a trial relaxes the chain from the last pinned configuration found (below
-  the critical one, so the line only moves forward) at the trial drive, in
-  chunks of Euler steps;
-- it is pinned when no site moved by more than chunk * dt * tol_force during
-  a chunk (the mean force per site over the chunk is below tol_force);
-- it is depinned when every site has advanced by at least M: a forward-moving
-  line never passes a pinned configuration, and the translates by M of a
-  pinned configuration are pinned too, so none exists at that drive.
+`critical_forces` calls the library's no-passing solver (qew_critical_force):
+every sample is bisected on f on the device in one launch, each trial drive
+decided by moving sites forward to the first zeros of their own forces (which
+never passes a pinned configuration) until the line is pinned or has advanced
+by M.  Nothing is integrated in time and nothing returns to the host between
+trials.
 
-The host only compares states between chunks (no force is evaluated here);
-every Euler step and measurement runs in the library's kernels.
+`critical_forces_euler` is the earlier driver kept for comparison: the same
+bisection, each trial an Euler relaxation of Eq. (1) through qew_run in chunks
+of steps, decided on the host between chunks:
+- pinned when no site moved by more than chunk * dt * tol_force during a
+  chunk (the mean force per site over the chunk is below tol_force);
+- depinned when every site has advanced by at least M.
 """
 import numpy as np
 
@@ -57,9 +57,40 @@ def _relax(kind, L, M, f, dids, u, u_ref, seed, strength, c, dt, chunk, max_step
     return status, steps
 
 
+STATUS = {0: "done", 1: "no pinned configuration at the lower drive",
+          2: "a trial undecided within max_sweeps", 3: "out of bisection rounds"}
+
+
 def critical_forces(kind, L, M, disorder_ids, seed, f_lo=0.0, f_hi=5.0, tol_f=1e-6,
-                    tol_force=1e-10, strength=1.0, c=1.0, dt=0.05, chunk=2048,
-                    max_steps=4_000_000):
+                    tol_force=1e-10, strength=1.0, c=1.0, max_sweeps=2_000_000, u0=None):
+    """f_c^s of every sample (disorder id) of length L and period M by the
+    library's no-passing solver.  Returns dict(f_lo [S], f_hi [S], u_c [S][L],
+    sweeps [S]): f_c^s lies in [f_lo, f_hi) with f_hi - f_lo < tol_f, u_c is the
+    pinned configuration at f_lo.  u0: start configurations (default flat)."""
+    import torch
+    dids = np.asarray(disorder_ids, np.uint32)
+    S = dids.size
+    dev = torch.device("cuda")
+    d_did = torch.from_numpy(dids.astype(np.int64)).to(torch.int32).to(dev)
+    u = np.zeros((S, int(L))) if u0 is None else np.array(u0, np.float64).reshape(S, int(L))
+    d_u = torch.from_numpy(np.ascontiguousarray(u)).to(dev)
+    d_f = torch.zeros((S, 2), dtype=torch.float64, device=dev)
+    d_st = torch.zeros((S, 2), dtype=torch.int64, device=dev)
+    qew.qew_critical_force(kind, strength, seed, M, c, d_did, f_lo, f_hi, tol_f, tol_force, max_sweeps,
+                           d_u, d_f, d_st, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    st = d_st.cpu().numpy()
+    bad = st[:, 0] != 0
+    if np.any(bad):
+        s = int(np.flatnonzero(bad)[0])
+        raise RuntimeError(f"critical force of sample {s}: {STATUS.get(int(st[s, 0]), st[s, 0])}")
+    f = d_f.cpu().numpy()
+    return {"f_lo": f[:, 0], "f_hi": f[:, 1], "u_c": d_u.cpu().numpy(), "sweeps": st[:, 1]}
+
+
+def critical_forces_euler(kind, L, M, disorder_ids, seed, f_lo=0.0, f_hi=5.0, tol_f=1e-6,
+                          tol_force=1e-10, strength=1.0, c=1.0, dt=0.05, chunk=2048,
+                          max_steps=4_000_000):
     """Bisect f_c^s of every sample (disorder id) of length L and period M.
     Returns dict(f_lo [S], f_hi [S], u_c [S][L], rounds, steps): f_c^s lies in
     [f_lo, f_hi) with f_hi - f_lo < tol_f, u_c is the pinned configuration at
@@ -103,7 +134,7 @@ def main(argv=None):
     import torch
 
     from . import std
-    ap = argparse.ArgumentParser(description="f_c^s of periodic samples (bisection on the GPU)")
+    ap = argparse.ArgumentParser(description="f_c^s of periodic samples on the GPU")
     ap.add_argument("--kind", type=int, default=1)
     ap.add_argument("--L", type=int, default=256)
     ap.add_argument("--M", type=int, default=256)
@@ -111,9 +142,12 @@ def main(argv=None):
     ap.add_argument("--tol-f", type=float, default=1e-5)
     ap.add_argument("--f-hi", type=float, default=4.0)
     ap.add_argument("--seed", type=int, default=workloads.SEED_BASE + 9)
+    ap.add_argument("--method", choices=("no-passing", "euler"), default="no-passing")
     a = ap.parse_args(argv)
+    solve = critical_forces if a.method == "no-passing" else critical_forces_euler
+    solve(a.kind, a.L, a.M, np.arange(1), a.seed, f_hi=a.f_hi, tol_f=1e-2)  # warm-up (library load, kernels)
     t0 = time.perf_counter()
-    r = critical_forces(a.kind, a.L, a.M, np.arange(a.samples), a.seed, f_hi=a.f_hi, tol_f=a.tol_f)
+    r = solve(a.kind, a.L, a.M, np.arange(a.samples), a.seed, f_hi=a.f_hi, tol_f=a.tol_f)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # structure factor of the critical configurations, on the device
@@ -131,11 +165,11 @@ def main(argv=None):
     q = 2 * np.pi * np.arange(1, a.L // 2 + 1) / a.L
     n_fit = max(a.L // 16, 4)
     _, slope = std.power_law_fit(q[:n_fit], sq[:n_fit])
-    print(json.dumps({"kind": a.kind, "L": a.L, "M": a.M, "samples": a.samples,
-                      "f_c_mean": float(r["f_lo"].mean()), "f_c_std": float(r["f_lo"].std()),
-                      "f_c": r["f_lo"].tolist(), "rounds": r["rounds"], "steps": r["steps"],
-                      "seconds": round(wall, 2),
-                      "site_updates_per_s": a.L * a.samples * r["steps"] / wall,
+    work = ({"sweeps_per_sample": r["sweeps"].tolist()} if a.method == "no-passing" else
+            {"rounds": r["rounds"], "euler_steps": r["steps"]})
+    print(json.dumps({"method": a.method, "kind": a.kind, "L": a.L, "M": a.M, "samples": a.samples,
+                      "tol_f": a.tol_f, "f_c_mean": float(r["f_lo"].mean()), "f_c_std": float(r["f_lo"].std()),
+                      "f_c": r["f_lo"].tolist(), "seconds": round(wall, 3), **work,
                       "zeta_from_sq": round((-slope - 1) / 2, 4), "sq_fit_modes": n_fit}))
 
 

@@ -86,6 +86,22 @@ hipError_t launch_force_eval(int kind, double strength, uint32_t k0, uint32_t k1
                              const uint32_t* did, const int32_t* j, const int32_t* cell,
                              const double* frac, double* out, int64_t n, hipStream_t st);
 
+// Critical force and configuration of samples periodic in u (one workgroup
+// per sample, the whole bisection in one launch).  u_io [S][L]: start in,
+// last pinned configuration out; f_out [S][2]: the final bracket; st_out
+// [S][2]: status (0 done, 1 no pinned configuration at the lower drive, 2 a
+// trial undecided within max_sweeps, 3 out of rounds) and sweeps made.
+struct CritParams {
+  int32_t L, period, max_rounds;
+  uint32_t k0, k1;
+  double c, strength, f_lo, f_hi, tol_f, tol_force;
+  int64_t max_sweeps;
+};
+constexpr int kCritMaxL = 4096;
+size_t critical_lds_bytes(int L);
+hipError_t launch_critical(int kind, const CritParams& q, int n_samples, const uint32_t* did, double* u_io,
+                           double* f_out, int64_t* st_out, hipStream_t st);
+
 // Structure factor at one measurement: pack, FFT passes, per-mode |U_n/L|^2,
 // binned mean over samples into out[n_bins].  Every L_s equals L (power of
 // two); u_plain != nullptr selects the FP64 state, else `split`.

@@ -1210,6 +1210,41 @@ qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, in
   return QEW_OK;
 }
 
+qew_status qew_critical_force(int32_t kind, double strength, uint64_t seed, int32_t period, double c,
+                              int32_t n_samples, int32_t L, const uint32_t* d_did, double f_lo, double f_hi,
+                              double tol_f, double tol_force, int64_t max_sweeps, double* d_u, double* d_f,
+                              int64_t* d_status, void* stream) {
+  g_err.clear();
+  if (kind != QEW_RF_CR_UNIFORM && kind != QEW_RB_CR_GAUSS)
+    return fail(QEW_EUNSUPPORTED, "the critical force needs a Catmull-Rom kind (continuous forces)");
+  if (!(std::isfinite(strength) && strength >= 0)) return fail(QEW_EINVAL, "strength must be finite and >= 0");
+  if (period < 1 || period >= (1 << 30)) return fail(QEW_EINVAL, "the sample must be periodic in u: 1 <= period < 2^30");
+  if (!(std::isfinite(c) && c > 0)) return fail(QEW_EINVAL, "c must be finite and > 0");
+  if (n_samples < 1) return fail(QEW_EINVAL, "n_samples must be >= 1");
+  if (L < 3 || L > kCritMaxL) return fail(QEW_EINVAL, "L must be in [3, %d]", kCritMaxL);
+  if (!(std::isfinite(f_lo) && std::isfinite(f_hi) && f_lo < f_hi)) return fail(QEW_EINVAL, "need finite f_lo < f_hi");
+  if (!(tol_f > 0) || !(tol_force > 0)) return fail(QEW_EINVAL, "tol_f and tol_force must be > 0");
+  if (max_sweeps < 4) return fail(QEW_EINVAL, "max_sweeps must be >= 4");
+  const double rounds = std::ceil(std::log2((f_hi - f_lo) / tol_f)) + 1.0;
+  if (!(rounds <= 200.0)) return fail(QEW_EINVAL, "(f_hi - f_lo) / tol_f needs more than 200 bisection rounds");
+  if (!d_did || !d_u || !d_f || !d_status) return fail(QEW_EINVAL, "NULL device pointer");
+  CritParams q;
+  q.L = L;
+  q.period = period;
+  q.max_rounds = (int)std::max(rounds, 1.0);
+  q.k0 = (uint32_t)(seed & 0xffffffffu);
+  q.k1 = (uint32_t)(seed >> 32);
+  q.c = c;
+  q.strength = strength;
+  q.f_lo = f_lo;
+  q.f_hi = f_hi;
+  q.tol_f = tol_f;
+  q.tol_force = tol_force;
+  q.max_sweeps = max_sweeps;
+  QEW_HIP(launch_critical(kind, q, n_samples, d_did, d_u, d_f, d_status, static_cast<hipStream_t>(stream)));
+  return QEW_OK;
+}
+
 void qew_plan_destroy(qew_plan_t* p) {
   if (!p) return;
   drop_graphs(p);

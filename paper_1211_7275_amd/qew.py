@@ -35,7 +35,8 @@ QEW_FLAG_FUSED_SPARSE = 8
 
 EXPORTS = ("qew_plan", "qew_workspace_bytes", "qew_plan_info_get", "qew_autotune", "qew_run",
            "qew_run_noalloc", "qew_ensemble", "qew_sq_get", "qew_run_stats_get", "qew_read_state", "qew_write_state",
-           "qew_debug_philox_fill", "qew_debug_force_eval", "qew_plan_destroy", "qew_last_error")
+           "qew_debug_philox_fill", "qew_debug_force_eval", "qew_critical_force", "qew_plan_destroy",
+           "qew_last_error")
 
 ENSEMBLE_ROWS = ("v", "v_se", "w2", "w2_se", "ubar", "ubar_se", "w2_about_ensemble_ubar")
 
@@ -108,6 +109,11 @@ def _load():
                                          ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
                                          ctypes.c_int64, vp]
     lib.qew_debug_force_eval.restype = st
+    lib.qew_critical_force.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                       vp, vp, vp, vp]
+    lib.qew_critical_force.restype = st
     lib.qew_plan_destroy.argtypes = [vp]
     lib.qew_plan_destroy.restype = None
     lib.qew_last_error.argtypes = []
@@ -218,6 +224,18 @@ def qew_debug_force_eval(kind, strength, seed, precision, d_did, d_j, d_cell, d_
                                      d_did.data_ptr(), d_j.data_ptr(), d_cell.data_ptr(),
                                      d_frac.data_ptr(), d_out.data_ptr(), d_out.numel(),
                                      _stream_ptr(stream)), "qew_debug_force_eval")
+
+
+def qew_critical_force(kind, strength, seed, period, c, d_did, f_lo, f_hi, tol_f, tol_force, max_sweeps,
+                       d_u, d_f, d_status, stream=None):
+    """d_did: [S] uint32, d_u: [S, L] float64 (start in, pinned configuration out),
+    d_f: [S, 2] float64 out, d_status: [S, 2] int64 out (device tensors)."""
+    S, L = d_u.shape
+    _check(_lib.qew_critical_force(int(kind), float(strength), int(seed) & 0xFFFFFFFFFFFFFFFF, int(period),
+                                   float(c), int(S), int(L), d_did.data_ptr(), float(f_lo), float(f_hi),
+                                   float(tol_f), float(tol_force), int(max_sweeps), d_u.data_ptr(),
+                                   d_f.data_ptr(), d_status.data_ptr(), _stream_ptr(stream)),
+           "qew_critical_force")
 
 
 def qew_plan_destroy(plan):

@@ -202,3 +202,29 @@ def test_run_noalloc_rejects_before_any_device_work():
     big = workloads.custom(0, [64] * 64, 1.0, 6000, np.arange(1, 6001), 1)  # 9.2 MB of series
     st, msg = status(big, precision=qew.QEW_FP64_PLAIN, path=qew.QEW_ONE_STEP)
     assert st == qew.QEW_ENOMEM and "scratch array holds 8388608" in msg
+
+
+def test_critical_force_argument_checks():
+    """qew_critical_force validates on the host before any device call."""
+    lib = qew.lib()
+    ptr = ctypes.c_void_p(256)  # never dereferenced: every case fails validation first
+
+    def st(kind=1, strength=1.0, period=64, c=1.0, S=1, L=64, f_lo=0.0, f_hi=4.0, tol_f=1e-4,
+           tol_force=1e-10, max_sweeps=1000, null=False):
+        p = None if null else ptr
+        return lib.qew_critical_force(kind, strength, 1, period, c, S, L, p, f_lo, f_hi, tol_f, tol_force,
+                                      max_sweeps, p, p, p, None)
+
+    assert st(kind=2) == qew.QEW_EUNSUPPORTED and "Catmull-Rom" in qew.qew_last_error()
+    assert st(kind=3) == qew.QEW_EUNSUPPORTED
+    assert st(period=0) == qew.QEW_EINVAL and "periodic" in qew.qew_last_error()
+    assert st(strength=-1.0) == qew.QEW_EINVAL
+    assert st(c=0.0) == qew.QEW_EINVAL
+    assert st(S=0) == qew.QEW_EINVAL
+    assert st(L=2) == qew.QEW_EINVAL and st(L=4097) == qew.QEW_EINVAL
+    assert st(f_lo=1.0, f_hi=1.0) == qew.QEW_EINVAL
+    assert st(f_hi=float("inf")) == qew.QEW_EINVAL
+    assert st(tol_f=0.0) == qew.QEW_EINVAL and st(tol_force=-1.0) == qew.QEW_EINVAL
+    assert st(max_sweeps=3) == qew.QEW_EINVAL
+    assert st(tol_f=1e-300) == qew.QEW_EINVAL and "200" in qew.qew_last_error()
+    assert st(null=True) == qew.QEW_EINVAL
