@@ -314,17 +314,24 @@ def summarize_profile(run_dir, copy_dir_fetch=None, copy_dir_write=None):
     trace = rows("*kernel_trace.csv")
     if trace:
         trace.sort(key=lambda r: int(r["Start_Timestamp"]))
-        for init, tag in (("k_init_split", "k_step_fused"), ("k_init_plain", "k_step_plain")):
+        # The timed run of a path starts at its last initialisation kernel and
+        # runs until the other path's first initialisation after it (or the end).
+        for init, other in (("k_init_split", "k_init_plain"), ("k_init_plain", "k_init_split")):
             idx = [i for i, r in enumerate(trace) if init in r["Kernel_Name"]]
             if not idx:
                 continue
-            seg = [r for r in trace[idx[-1]:] if tag in r["Kernel_Name"]]
+            seg = []
+            for r in trace[idx[-1] + 1:]:
+                if other in r["Kernel_Name"]:
+                    break
+                seg.append(r)
             by_name = {}  # each kernel (e.g. each variant of the fused kernel) on its own line
             for r in seg:
                 by_name.setdefault(short(r["Kernel_Name"]), []).append(
                     (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
             for name, d in by_name.items():
-                lines.append(f"\ntimed run: `{name}` {len(d)} launches, average {sum(d) / len(d):.5f} ms")
+                lines.append(f"\ntimed run: `{name}` {len(d)} launches, average {sum(d) / len(d):.5f} ms, "
+                             f"total {sum(d):.3f} ms")
     counters = rows("*counter_collection.csv")
     if counters:
         # one record per dispatch: name, duration, counter sums
@@ -447,6 +454,11 @@ def other_workload(qew, args):
             "v_last_mean": float(np.nanmean(out["v"][:, -1])) if out["v"].shape[1] else None}
 
 
+def progress(*a):
+    """Phase lines on stderr (the JSON line alone goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,11 +473,16 @@ def main():
     ap.add_argument("--plain-window", type=int, default=20_000,
                     help="Euler steps the FP64 plain leg is timed on (0: the whole horizon)")
     ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--only-plain", action="store_true",
+                    help="time only the FP64 plain leg (profiler runs of that kernel)")
     ap.add_argument("--skip-cpu", action="store_true",
                     help="skip the oracle leg (and with it the error against the oracle)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--k", type=int, default=None, help=f"steps per fused launch (default {BENCH_K}; 0: autotune)")
     ap.add_argument("--tile", type=int, default=None, help=f"sites per fused tile (default {BENCH_TILE}; 0: autotune)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every kernel directly instead of replaying hipGraphs (the same "
+                         "kernels and dispatches; for profiler counter runs)")
     ap.add_argument("--fused-variant", default="auto", choices=("auto", "dense", "sparse"),
                     help="other workloads: the fused kernel variant (auto: chosen from the "
                          "measured velocities before each stretch between measurements)")
@@ -517,6 +534,13 @@ def main():
         print(json.dumps(other_workload(qew, args)), flush=True)
         return
 
+    if args.only_plain:
+        H = int(args.horizon)
+        gflags = qew.QEW_FLAG_NO_GRAPH if args.no_graph else 0
+        print(json.dumps({"metric": "FP64 plain one-step path on the benchmark workload (window)",
+                          "fp64_plain": plain_leg(qew, args, H, gflags)}), flush=True)
+        return
+
     k = BENCH_K if args.k is None else args.k
     tile = BENCH_TILE if args.tile is None else args.tile
     H = int(args.horizon)
@@ -525,12 +549,16 @@ def main():
     # 1. The oracle on the host: its rate, and the reference for the error of both paths.
     oracle_run = None
     if not args.skip_cpu:
+        progress("oracle on the host cores")
         line_extra["cpu_baseline"], oracle_run = cpu_baseline(p, args.cpu_seconds)
+        progress("error of both GPU paths against the oracle,", oracle_run["steps"], "steps")
         line_extra["error_vs_oracle"] = c3_parity(qew, p, oracle_run, k, tile)
     # 2. The timed run: the whole horizon after the warm-up, fused FP32 split.
     warm_steps = min(H, int(round(args.warmup * H / args.steps)))
+    gflags = qew.QEW_FLAG_NO_GRAPH if args.no_graph else 0
+    progress("warm-up of", warm_steps, "Euler steps, then the timed run of", H)
     out, st, info, wall = time_path(qew, p, qew.QEW_FP32_SPLIT, qew.QEW_FUSED, max(warm_steps, 1),
-                                    k=k, tile=tile)
+                                    k=k, tile=tile, flags=gflags)
     sites = info.total_sites
     value = sites * H / wall
     roof = fused_roofline(p["kind"], st, info, out, H)
@@ -554,29 +582,36 @@ def main():
             "euler_steps_per_step": H / args.steps, "warmup_euler_steps": warm_steps,
             "measurements": int(len(p["meas_steps"])),
             "path": "fp32-split fused temporally blocked", "k": info.k, "tile": info.tile,
-            "autotuned": bool(info.autotuned),
+            "autotuned": bool(info.autotuned), "graphs": not args.no_graph,
         },
         "roofline": roof,
     }
+    progress("timed run:", round(wall, 3), "s")
     # 3. The FP64 plain one-step path on a window with the same measurement density.
     if not args.skip_plain:
-        win = H if args.plain_window <= 0 else min(int(args.plain_window), H)
-        pp = bench_problem(H) if win == H else window_problem(win)
-        out2, st2, info2, wall2 = time_path(qew, pp, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 64)
-        plain_value = info2.total_sites * win / wall2
-        line["fp64_plain"] = {
-            "value": round(plain_value, 1), "unit": "site-updates/s", "euler_steps_timed": win,
-            "measurements": int(len(pp["meas_steps"])),
-            "window": "the whole horizon" if win == H else
-                      f"Euler steps 1..{win} of the workload with {len(pp['meas_steps'])} log-spaced "
-                      f"measurements (the full run's 200 per 10^6 steps); the plain kernel's cost per "
-                      f"step does not depend on the state, so the rate holds for the whole horizon",
-            "ms_per_euler_step": round(wall2 * 1e3 / win, 6),
-            "roofline": plain_roofline(st2, info2, win),
-        }
-        line["speedup_vs_fp64_plain"] = round(value / plain_value, 3)
+        line["fp64_plain"] = plain_leg(qew, args, H, gflags)
+        line["speedup_vs_fp64_plain"] = round(value / line["fp64_plain"]["value"], 3)
     line.update(line_extra)
     print(json.dumps(line), flush=True)
+
+
+def plain_leg(qew, args, H, gflags):
+    """The FP64 plain one-step path timed on a window of the workload with
+    the full run's measurement density."""
+    win = H if args.plain_window <= 0 else min(int(args.plain_window), H)
+    progress("FP64 plain path over", win, "Euler steps")
+    pp = bench_problem(H) if win == H else window_problem(win)
+    out2, st2, info2, wall2 = time_path(qew, pp, qew.QEW_FP64_PLAIN, qew.QEW_ONE_STEP, 64, flags=gflags)
+    return {
+        "value": round(info2.total_sites * win / wall2, 1), "unit": "site-updates/s", "euler_steps_timed": win,
+        "measurements": int(len(pp["meas_steps"])),
+        "window": "the whole horizon" if win == H else
+                  f"Euler steps 1..{win} of the workload with {len(pp['meas_steps'])} log-spaced "
+                  f"measurements (the full run's 200 per 10^6 steps); the plain kernel's cost per "
+                  f"step does not depend on the state, so the rate holds for the whole horizon",
+        "ms_per_euler_step": round(wall2 * 1e3 / win, 6),
+        "roofline": plain_roofline(st2, info2, win),
+    }
 
 
 if __name__ == "__main__":

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_init_plain(Tables t, double* u) {
 
 template <int KIND>
 __global__ void __launch_bounds__(kBlock)
-    k_init_split(Tables t, SplitBuf b, Phys ph, int with_nodes, int keep_state) {
+    k_init_split(Tables t, SplitBuf b, Phys ph, int with_nodes) {
   const int tile = blockIdx.x;
   const int s = t.mt_s[tile];
   const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
@@ -103,13 +103,9 @@ __global__ void __launch_bounds__(kBlock)
   const uint32_t id = t.did[s];
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
-    int32_t c = 0;
-    if (keep_state) {
-      c = b.cell[base + j];
-    } else {
-      b.cell[base + j] = 0;
-      b.frac[base + j] = 0.0f;
-    }
+    const int32_t c = 0;
+    b.cell[base + j] = 0;
+    b.frac[base + j] = 0.0f;
     if (with_nodes) {
       float4 nd;
       nd.x = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1, ph.period);
@@ -118,6 +114,27 @@ __global__ void __launch_bounds__(kBlock)
       nd.w = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period);
       b.nodes[base + j] = nd;
     }
+  }
+}
+
+// Rebuild of the fused path's node cache for the state in `b` (after
+// one-step stretches or a written state): the nodes of every site's cell.
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_refresh_nodes(Tables t, SplitBuf b, Phys ph) {
+  const int tile = blockIdx.x;
+  const int s = t.mt_s[tile];
+  const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
+  const int64_t base = t.off[s];
+  const uint32_t id = t.did[s];
+  for (int q = threadIdx.x; q < len; q += kBlock) {
+    const int j = p0 + q;
+    const int32_t c = b.cell[base + j];
+    float4 nd;
+    nd.x = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1, ph.period);
+    nd.y = node_f32<KIND>(j, c, id, ph.k0, ph.k1, ph.period);
+    nd.z = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1, ph.period);
+    nd.w = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period);
+    b.nodes[base + j] = nd;
   }
 }
 
@@ -825,13 +842,13 @@ hipError_t launch_init_plain(const Tables& t, double* u, hipStream_t st) {
 
 hipError_t launch_init_split(const Tables& t, SplitBuf b, const Phys& ph, int kind, bool nodes,
                              hipStream_t st) {
-  QEW_KIND_DISPATCH(kind, k_init_split, dim3(t.n_mt), dim3(kBlock), 0, st, t, b, ph, nodes ? 1 : 0, 0);
+  QEW_KIND_DISPATCH(kind, k_init_split, dim3(t.n_mt), dim3(kBlock), 0, st, t, b, ph, nodes ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_refresh_nodes(const Tables& t, SplitBuf b, const Phys& ph, int kind,
                                 hipStream_t st) {
-  QEW_KIND_DISPATCH(kind, k_init_split, dim3(t.n_mt), dim3(kBlock), 0, st, t, b, ph, 1, 1);
+  QEW_KIND_DISPATCH(kind, k_refresh_nodes, dim3(t.n_mt), dim3(kBlock), 0, st, t, b, ph);
   return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ def test_summarizer_splits_kernel_variants(tmp_path):
     text = bench.summarize_profile(str(tmp_path))
     assert "timed run: `qew::k_step_fused<0, 8, false>` 2 launches, average 2.00000 ms" in text
     assert "timed run: `qew::k_step_fused<0, 8, true>` 3 launches, average 5.00000 ms" in text
+    assert "timed run: `qew::k_meas_split<0>` 1 launches" in text
 
 
 def test_summarizer_counters_per_variant(tmp_path):
