@@ -80,6 +80,7 @@ def kernel_source_hash():
     (every dense k_step_fused instantiation) in the gfx950 code object of the
     built library: it changes exactly when that kernel's compiled code does."""
     import hashlib
+    import re
     import struct
     lib = os.path.join(ROOT, "paper_1211_7275_amd", "lib", "libqew.so")
     with open(lib, "rb") as fh:
@@ -106,8 +107,8 @@ def kernel_source_hash():
         st_name, st_info, st_other, st_shndx, st_value, st_size = struct.unpack_from(
             "<IBBHQQ", code, sym_off + 24 * i)
         name = code[str_off + st_name:code.index(b"\0", str_off + st_name)]
-        # the dense variant (template flag false) is the kernel the benchmark runs
-        if b"k_step_fused" in name and b"Lb0E" in name and st_size > 0 and not name.endswith(b".kd"):
+        # the dense variant (third template argument false) is the kernel the benchmark runs
+        if re.search(rb"k_step_fusedILi\d+ELi\d+ELb0E", name) and st_size > 0 and not name.endswith(b".kd"):
             syms.append((name, st_value, st_size))
     for name, value, size in sorted(syms):
         start = text_off + (value - text_addr)

@@ -301,6 +301,10 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
   asm volatile("" : "+v"(cel));
   asm volatile("" : "+v"(dt));
   const float g = ph.sgn_strf;
+  // Unit disorder strength (g = +1 for force values, -1 for potential
+  // values): the service pass then forms the coefficients without the four
+  // multiplications by g (exactly the same values).
+  const bool unit_g = g == kind_sign<KIND>();
   lds_f32* eb = (lds_f32*)&s_edge[0][0][wv][0];  // slot wv: the left neighbour's entries
   asm volatile("" : "+v"(eb));
   // entry of parity `pa`, word q (0 cell, 1 offset), slot wv + ds, end e
@@ -321,6 +325,9 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
     if (start_mod < 0) start_mod += L;
     constexpr int VW = (P % 4 == 0) ? 4 : 2;  // sites per vector load / store
     const bool contiguous = start >= 0 && start + T <= L && (start % VW) == 0;
+    // The tile crosses the end of its chain: only then does a site's column
+    // need wrapping in the service pass.
+    const bool wraps = start_mod + T > L;
     const int32_t cbase = uniform_i32(in.cell[base + start_mod]);
 
     float c[P];  // cell - cbase, an exact integer
@@ -490,8 +497,10 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
           const int32_t cell = cbase + (int32_t)cnew;
           const int lp = (int)(((uint32_t)ni % kBlock) * P + (uint32_t)ni / kBlock);  // tile-local position
           int j = start_mod + lp;
-          if (j >= L) j -= L;
-          if (j >= L) j %= L;
+          if (wraps) {
+            if (j >= L) j -= L;
+            if (j >= L) j %= L;
+          }
           float4 w4 = s_nodes[ni];
           if (move == 1.0f) {
             w4 = make_float4(w4.y, w4.z, w4.w, node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1, ph.period));
@@ -504,7 +513,9 @@ __global__ void __launch_bounds__(kBlock, fused_min_waves(P))
                              node_f32<KIND>((uint32_t)j, cell + 2, id, ph.k0, ph.k1, ph.period));
           }
           s_nodes[ni] = w4;
-          const float4 co = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w, g, f);
+          float4 co;
+          if (unit_g) co = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w, kind_sign<KIND>(), f);
+          else co = spline_coef<KIND>(w4.x, w4.y, w4.z, w4.w, g, f);
           s_req[slot] = make_int4(__float_as_int(co.x), __float_as_int(co.y), __float_as_int(co.z),
                                   __float_as_int(co.w));
         }
