@@ -155,6 +155,18 @@ __device__ __forceinline__ float node_f32(uint32_t j, int32_t n, uint32_t id, ui
   }
 }
 
+// The same with the round keys of `keys` (vector registers).
+template <int KIND>
+__device__ __forceinline__ float node_f32(uint32_t j, int32_t n, uint32_t id, const VectorKeys& keys,
+                                          int32_t period) {
+  const NodeWords w = node_words(j, wrap_cell(n, period), id, keys);
+  if constexpr (KIND == kRF) {
+    return (float)rf_odd(w.x0) * 0x1p-24f;
+  } else {
+    return rb_value_f32(w.x0, w.x1);
+  }
+}
+
 template <int KIND>
 __device__ __forceinline__ double node_f64(uint32_t j, int32_t n, uint32_t id, uint32_t k0,
                                            uint32_t k1, int32_t period) {

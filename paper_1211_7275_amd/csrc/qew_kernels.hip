@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(kBlock)
   const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
   const int64_t base = t.off[s];
   const uint32_t id = t.did[s];
+  const VectorKeys keys = vector_keys(ph.k0, ph.k1);
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
     const int32_t c = 0;
@@ -108,10 +109,10 @@ __global__ void __launch_bounds__(kBlock)
     b.frac[base + j] = 0.0f;
     if (with_nodes) {
       float4 nd;
-      nd.x = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1, ph.period);
-      nd.y = node_f32<KIND>(j, c, id, ph.k0, ph.k1, ph.period);
-      nd.z = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1, ph.period);
-      nd.w = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period);
+      nd.x = node_f32<KIND>(j, c - 1, id, keys, ph.period);
+      nd.y = node_f32<KIND>(j, c, id, keys, ph.period);
+      nd.z = node_f32<KIND>(j, c + 1, id, keys, ph.period);
+      nd.w = node_f32<KIND>(j, c + 2, id, keys, ph.period);
       b.nodes[base + j] = nd;
     }
   }
@@ -126,14 +127,15 @@ __global__ void __launch_bounds__(kBlock) k_refresh_nodes(Tables t, SplitBuf b, 
   const int p0 = t.mt_p0[tile], len = t.mt_len[tile];
   const int64_t base = t.off[s];
   const uint32_t id = t.did[s];
+  const VectorKeys keys = vector_keys(ph.k0, ph.k1);
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
     const int32_t c = b.cell[base + j];
     float4 nd;
-    nd.x = node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1, ph.period);
-    nd.y = node_f32<KIND>(j, c, id, ph.k0, ph.k1, ph.period);
-    nd.z = node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1, ph.period);
-    nd.w = node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period);
+    nd.x = node_f32<KIND>(j, c - 1, id, keys, ph.period);
+    nd.y = node_f32<KIND>(j, c, id, keys, ph.period);
+    nd.z = node_f32<KIND>(j, c + 1, id, keys, ph.period);
+    nd.w = node_f32<KIND>(j, c + 2, id, keys, ph.period);
     b.nodes[base + j] = nd;
   }
 }
@@ -183,17 +185,18 @@ __global__ void __launch_bounds__(kBlock)
 
 template <int KIND>
 __device__ __forceinline__ void nodes_of(uint32_t j, int32_t c, uint32_t id, const Phys& ph,
-                                         float& p0, float& p1, float& p2, float& p3) {
+                                         const VectorKeys& keys, float& p0, float& p1, float& p2,
+                                         float& p3) {
   if (ph.strength == 0.0) {
     p0 = p1 = p2 = p3 = 0.0f;
     return;
   }
   // Catmull-Rom needs nodes c-1..c+2, Case 3 c..c+1, Case 4 c only.
   constexpr bool cubic = (KIND == kRF || KIND == kRB);
-  p0 = cubic ? node_f32<KIND>(j, c - 1, id, ph.k0, ph.k1, ph.period) : 0.0f;
-  p1 = node_f32<KIND>(j, c, id, ph.k0, ph.k1, ph.period);
-  p2 = (KIND != kRFPc) ? node_f32<KIND>(j, c + 1, id, ph.k0, ph.k1, ph.period) : 0.0f;
-  p3 = cubic ? node_f32<KIND>(j, c + 2, id, ph.k0, ph.k1, ph.period) : 0.0f;
+  p0 = cubic ? node_f32<KIND>(j, c - 1, id, keys, ph.period) : 0.0f;
+  p1 = node_f32<KIND>(j, c, id, keys, ph.period);
+  p2 = (KIND != kRFPc) ? node_f32<KIND>(j, c + 1, id, keys, ph.period) : 0.0f;
+  p3 = cubic ? node_f32<KIND>(j, c + 2, id, keys, ph.period) : 0.0f;
 }
 
 // MEAS: also write the measurement partial of the input state, as
@@ -212,6 +215,7 @@ __global__ void __launch_bounds__(kBlock)
   const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
   const int32_t Kc = MEAS ? in.cell[base + p0] : 0;
   const double Kr = MEAS ? (double)in.frac[base + p0] : 0.0;
+  const VectorKeys keys = vector_keys(ph.k0, ph.k1);
   double sf = 0.0, s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(kBlock)
     int32_t c = in.cell[base + j];
     float r = in.frac[base + j];
     float n0, n1, n2, n3;
-    nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+    nodes_of<KIND>((uint32_t)j, c, id, ph, keys, n0, n1, n2, n3);
     const float4 a = spline_coef<KIND>(n0, n1, n2, n3, sp.sgn_str, f);
     const float F = split_force<KIND>(c, r, in.cell[base + jm], in.frac[base + jm],
                                       in.cell[base + jp], in.frac[base + jp], a, sp.c);
@@ -660,6 +664,7 @@ __global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phy
   const SplitPhys sp{ph.cf, ph.dtf, ph.sgn_strf};
   const int32_t Kc = b.cell[base + p0];  // shift: the tile's first site
   const double Kr = (double)b.frac[base + p0];
+  const VectorKeys keys = vector_keys(ph.k0, ph.k1);
   double sf = 0.0, s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < len; q += kBlock) {
     const int j = p0 + q;
@@ -675,7 +680,7 @@ __global__ void __launch_bounds__(kBlock) k_meas_split(Tables t, SplitBuf b, Phy
       n2 = nd.z;
       n3 = nd.w;
     } else {
-      nodes_of<KIND>((uint32_t)j, c, id, ph, n0, n1, n2, n3);
+      nodes_of<KIND>((uint32_t)j, c, id, ph, keys, n0, n1, n2, n3);
     }
     const float4 a = spline_coef<KIND>(n0, n1, n2, n3, sp.sgn_str, f);
     const float F = split_force<KIND>(c, r, b.cell[base + jm], b.frac[base + jm], b.cell[base + jp],

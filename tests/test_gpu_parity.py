@@ -825,10 +825,11 @@ def test_fscan_gpu_matches_oracle(qew, oracle):
 # ----------------------------- critical force of periodic samples (Sec. III A)
 
 @pytest.mark.parametrize("kind,L,dids", [(0, 64, [0, 1, 2]), (1, 64, [0, 1, 2]), (0, 256, [0, 1]),
-                                         (1, 256, [0, 1])])
+                                         (1, 256, [0, 1]), (0, 63, [3]), (1, 63, [3, 4])])
 def test_critical_forces_match_oracle(qew, oracle, kind, L, dids):
     """The library's no-passing solver (one launch, no time integration)
-    against the oracle's bisection with Euler relaxations, L = M: the same
+    against the oracle's bisection with Euler relaxations, L = M (odd L = 63:
+    the site next to site 0 moves in a third phase of each sweep): the same
     bracket of f_c^s (every trial drive decided alike) and the same critical
     configuration per site (within 1e-6: both stop at |force| <= 1e-10 near
     the saddle-node, where the stiffness is small)."""
