@@ -244,3 +244,44 @@ def test_uneven_batch_full_horizon_eight_sizes(qew, oracle):
         say("  sample", s, "L", int(L[s]), "max site err", float(d.max()))
         assert d.max() <= 1e-3
         check_series(out, ref, s)
+
+
+# -------------------------- paper-scale chains over 10^3 steps, sampled sites
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_paper_scale_1000_steps_sampled_sites(qew, oracle, kind):
+    """L = 2^25 x 5 drives around the threshold (one shared disorder), fused
+    with the autotuned geometry, 10^3 steps with the workload's measurement
+    cadence: sites at tile edges, chain ends and random places of three
+    samples against the oracle's light-cone windows (2001 + 2 sites around
+    each, exact for the full chain), within 1e-3; d ubar = dt v between
+    consecutive measurement steps of a one-step stretch."""
+    N = 1000
+    p = workloads.config4(kind)
+    meas = p["meas_steps"]
+    p = dict(p, n_steps=N, meas_steps=meas[meas <= N])
+    L = int(p["L"][0])
+    say("L=2^25 x 5, kind", kind, "fused, autotuned,", N, "steps")
+    sim = qew.Simulation(p, precision=qew.QEW_FP32_SPLIT, path=qew.QEW_FUSED)
+    try:
+        out = sim.run()
+        info = sim.info()
+        say("  autotuned k", info.k, "tile", info.tile)
+        V = info.tile - 2 * info.k
+        rng = np.random.default_rng(40 + kind)
+        worst = 0.0
+        for s in (0, 2, 4):
+            u, step = sim.read_state(s)
+            assert step == N
+            picks = {0, L - 1, V - 1, V, 7 * V + 3, L // 2} | set(int(x) for x in rng.integers(0, L, 6))
+            for jj in sorted(picks):
+                ref = oracle.site_after(kind, 1.0, p["seed"], 0, L, jj, 1.0, 0.05, float(p["f"][s]), N)
+                worst = max(worst, abs(u[jj] - ref))
+                assert abs(u[jj] - ref) <= 1e-3, (s, jj)
+        say("  worst sampled site err", worst)
+    finally:
+        sim.close()
+    m = p["meas_steps"]
+    one = np.flatnonzero(np.diff(m) == 1)  # consecutive measurement steps
+    d = out["ubar"][:, one + 1] - out["ubar"][:, one]
+    assert np.max(np.abs(d - 0.05 * out["v"][:, one])) <= 1e-6
