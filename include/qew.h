@@ -99,7 +99,8 @@ typedef int32_t qew_status;
  */
 typedef struct qew_problem {
   int32_t         n_samples;    /* S >= 1                                               */
-  int32_t         kind;         /* QEW_RF_CR_UNIFORM or QEW_RB_CR_GAUSS                 */
+  int32_t         kind;         /* QEW_RF_CR_UNIFORM, QEW_RB_CR_GAUSS, QEW_RB_LIN_GAUSS
+                                   or QEW_RF_PC_GAUSS                                    */
   const int64_t  *L;            /* [S] chain lengths, 3 <= L_s <= 2^30                  */
   const double   *f;            /* [S] drive per sample (finite)                        */
   const uint32_t *disorder_id;  /* [S] Philox counter word 2; equal ids => same disorder */

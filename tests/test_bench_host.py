@@ -5,6 +5,9 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
@@ -76,3 +79,25 @@ def test_traffic_lookup_needs_the_measured_kernel_code(monkeypatch, tmp_path):
     assert bench.committed_traffic(48, 2048) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "00bb")  # kernel changed since
     assert bench.committed_traffic(56, 2048) is None
+
+
+def test_benchmark_problem_is_the_whole_workload():
+    """The timed run is the 10^6-step workload with its 200 log-spaced
+    measurements; a cut keeps the measurements inside it; the FP64 plain
+    window has the run's measurement density (200 per 10^6 steps)."""
+    p = bench.bench_problem(bench.HORIZON)
+    assert p["n_steps"] == 10**6 and len(p["meas_steps"]) == 200
+    assert p["meas_steps"][0] == 1 and p["meas_steps"][-1] == 10**6
+    assert list(p["L"]) == [1 << 22] * 4 and p["kind"] == 0 and p["f"][0] == 1.0
+    cut = bench.bench_problem(1000)
+    assert cut["n_steps"] == 1000 and np.all(cut["meas_steps"] <= 1000)
+    assert np.array_equal(cut["meas_steps"], p["meas_steps"][p["meas_steps"] <= 1000])
+    w = bench.window_problem(20_000)
+    assert w["n_steps"] == 20_000 and len(w["meas_steps"]) == 4 and w["meas_steps"][-1] == 20_000
+
+
+def test_error_metric_floors():
+    """v and ubar errors are relative to max(|x|, floor); w2 where positive."""
+    assert bench._rel([1.0 + 1e-9], [1.0], 1e-3) == pytest.approx(1e-9)
+    assert bench._rel([2e-6], [1e-6], 1e-3) == pytest.approx(1e-3)
+    assert bench._rel([], [], 1e-3) == 0.0
