@@ -71,7 +71,7 @@ def critical_forces(kind, L, M, disorder_ids, seed, f_lo=0.0, f_hi=5.0, tol_f=1e
     dids = np.asarray(disorder_ids, np.uint32)
     S = dids.size
     dev = torch.device("cuda")
-    d_did = torch.from_numpy(dids.astype(np.int64)).to(torch.int32).to(dev)
+    d_did = torch.from_numpy(dids.view(np.int32).copy()).to(dev)  # the uint32 ids, bit for bit
     u = np.zeros((S, int(L))) if u0 is None else np.array(u0, np.float64).reshape(S, int(L))
     d_u = torch.from_numpy(np.ascontiguousarray(u)).to(dev)
     d_f = torch.zeros((S, 2), dtype=torch.float64, device=dev)
