@@ -305,8 +305,10 @@ qew_status qew_debug_force_eval(int32_t kind, double strength, uint64_t seed, in
  * first relaxed at f_lo (each site moved to the nearest zero of its force in
  * the force's direction), then each trial drive starts from the last pinned
  * configuration and is decided pinned when every |force| <= tol_force,
- * depinned when every site advanced by M.  One workgroup per sample runs the
- * whole bisection in one launch, with the chain in LDS.
+ * depinned when every site advanced by M.  A site whose force is within
+ * tol_force / 4 of zero is not moved, and a move stops once the force left at
+ * the site is within tol_force / 64.  One workgroup per sample runs the whole
+ * bisection in one launch, with the chain in LDS.
  *   kind: QEW_RF_CR_UNIFORM or QEW_RB_CR_GAUSS (continuous forces; else
  *         QEW_EUNSUPPORTED).  Disorder as in qew_problem (Philox counter
  *         (j, n mod M, disorder id, 0), values times strength).

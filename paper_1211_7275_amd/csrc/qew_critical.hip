@@ -48,33 +48,56 @@ struct Cubic {
   __device__ double slope(double s) const { return b1 + s * (2.0 * b2 + s * (3.0 * b3)); }
 };
 
-// Zero of g on [lo, hi] where g is monotone with g(lo) > 0 >= g(hi) (up =
-// true) or g(lo) >= 0 > g(hi) (up = false): Newton steps kept inside the
-// bracket, halving it when a step leaves it, until the bracket is a few ulp
-// wide.  Returns lo (up: the last point with g > 0) or hi (the last with g < 0).
-__device__ double bracketed_zero(const Cubic& g, double lo, double hi, bool up) {
-  double x = 0.5 * (lo + hi);
+constexpr double kEps = 2.220446049250313e-16;
+
+// A point next to the zero of g on [lo, hi], where g is monotone with
+// g(lo) = glo > 0 >= g(hi) = ghi (up) or glo >= 0 > ghi (down).  The answer
+// lies on the near side of the zero -- g > 0 (up) or g < 0 (down) -- so a move
+// there never passes it.  Newton steps are taken from the end with the
+// smaller |g| and kept inside the bracket (a step that leaves it becomes the
+// midpoint).  When that end is the far-side one and already within `tol` of
+// zero, the next point is placed as far on the near side of the Newton
+// estimate of the zero as the end lies on the other side, so that a function
+// that keeps the Newton steps on the far side still yields a near-side point.
+// Stops once the near-side end has |g| <= tol or the bracket is a few ulp
+// wide.
+__device__ double bracketed_zero(const Cubic& g, double lo, double hi, double glo, double ghi, bool up,
+                                 double tol) {
   for (int it = 0; it < kBisect; ++it) {
+    const double gn = up ? glo : ghi;
+    if (fabs(gn) <= tol || hi - lo <= 4.0 * kEps) break;
+    const bool from_lo = fabs(glo) <= fabs(ghi);
+    const double e = from_lo ? lo : hi;
+    const double ge = from_lo ? glo : ghi;
+    const double d = g.slope(e);
+    double x = (d != 0.0) ? e - ge / d : 0.5 * (lo + hi);
+    if (from_lo != up && fabs(ge) <= tol) {
+      const double off = fmax(fabs(e - x), 4.0 * kEps);
+      x = up ? x - off : x + off;
+    }
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
     const double gx = g.at(x);
-    const bool left = up ? (gx > 0.0) : (gx >= 0.0);
-    if (left) lo = x;
-    else hi = x;
-    if (hi - lo <= 4.0 * 2.220446049250313e-16) break;
-    const double d = g.slope(x);
-    double nx = (d != 0.0) ? x - gx / d : 0.5 * (lo + hi);
-    if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
-    if (nx == x) break;
-    x = nx;
+    if (up ? (gx > 0.0) : (gx >= 0.0)) {
+      lo = x;
+      glo = gx;
+    } else {
+      hi = x;
+      ghi = gx;
+    }
   }
   return up ? lo : hi;
 }
 
+// The strength-scaled nodes n-1 .. n+2 of site j: the Catmull-Rom window of cell n.
 template <int KIND>
-__device__ Cubic local_force(uint32_t j, int32_t n, uint32_t id, uint32_t k0, uint32_t k1, int32_t period,
-                             double strength, double A, double c) {
-  double p[4];
+__device__ void node_window(uint32_t j, int32_t n, uint32_t id, const CritParams& q, double p[4]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) p[i] = strength * node_f64<KIND>(j, n - 1 + i, id, k0, k1, period);
+  for (int i = 0; i < 4; ++i) p[i] = q.strength * node_f64<KIND>(j, n - 1 + i, id, q.k0, q.k1, q.period);
+}
+
+// Local force in cell n from its window p.
+template <int KIND>
+__device__ Cubic cubic_of(const double p[4], int32_t n, double A, double c) {
   // Catmull-Rom in s: value = 1/2 [2 p1 + d1 s + d2 s^2 + d3 s^3]
   const double d1 = p[2] - p[0];
   const double d2 = 2.0 * p[0] - 5.0 * p[1] + 4.0 * p[2] - p[3];
@@ -123,55 +146,72 @@ __device__ int turning_points(const Cubic& g, double lo, double hi, double t[2])
   return m;
 }
 
-// First s in [s0, 1] where g (with g(s0) > 0) reaches 0, found on the
-// monotone piece that holds the crossing; returns the last point with g > 0
-// (so a move never steps past the zero), or -1 if g > 0 on all of [s0, 1].
-__device__ double first_zero_up(const Cubic& g, double s0) {
+// First s in [s0, 1] where g (with g(s0) = g0 > 0) reaches 0, found on the
+// monotone piece that holds the crossing; returns a point just short of it
+// (g > 0 there, so a move never steps past the zero), or -1 if g > 0 on all
+// of [s0, 1].
+__device__ double first_zero_up(const Cubic& g, double s0, double g0, double tol) {
   double t[2];
   const int m = turning_points(g, s0, 1.0, t);
-  double a = s0;
+  double a = s0, ga = g0;
   for (int i = 0; i <= m; ++i) {
     const double b = (i < m) ? t[i] : 1.0;
-    if (g.at(b) <= 0.0) return bracketed_zero(g, a, b, true);
+    const double gb = g.at(b);
+    if (gb <= 0.0) return bracketed_zero(g, a, b, ga, gb, true, tol);
     a = b;
+    ga = gb;
   }
   return -1.0;
 }
 
-// Last s in [0, s0] where g (with g(s0) < 0) is 0 going down; returns the
-// last point with g < 0 (the move stops short of the zero), or 2 if g < 0 on
-// all of [0, s0].
-__device__ double first_zero_down(const Cubic& g, double s0) {
+// Last s in [0, s0] where g (with g(s0) = g0 < 0) is 0 going down; returns a
+// point just short of it (g < 0 there), or 2 if g < 0 on all of [0, s0].
+__device__ double first_zero_down(const Cubic& g, double s0, double g0, double tol) {
   double t[2];
   const int m = turning_points(g, 0.0, s0, t);
-  double b = s0;
+  double b = s0, gb = g0;
   for (int i = m; i >= 0; --i) {
     const double a = (i > 0) ? t[i - 1] : 0.0;
-    if (g.at(a) >= 0.0) return bracketed_zero(g, a, b, false);
+    const double ga = g.at(a);
+    if (ga >= 0.0) return bracketed_zero(g, a, b, ga, gb, false, tol);
     b = a;
+    gb = ga;
   }
   return 2.0;
 }
 
 // Move of one site with its neighbours held: forward to the first zero of its
 // force ahead (dir > 0) or backward to the first zero behind (dir < 0),
-// starting at offset s of cell n whose local force is g.  Returns the new
-// position.
+// starting at offset s of cell n with window p and local force g, g0 = g(s).
+// A move into the next cell shifts the window by one node, so each cell
+// crossed costs one node.  Returns the new position; the force left there is
+// within `tol` of zero unless the bracket ran down to a few ulp first.
 template <int KIND>
-__device__ double relax_site(int32_t n, double s, Cubic g, double A, uint32_t j, uint32_t id,
-                             const CritParams& q, int dir) {
+__device__ double relax_site(int32_t n, double s, double g0, Cubic g, double p[4], double A, uint32_t j,
+                             uint32_t id, const CritParams& q, int dir, double tol) {
   for (int cell = 0; cell < kMaxCells; ++cell) {
-    if (cell > 0) g = local_force<KIND>(j, n, id, q.k0, q.k1, q.period, q.strength, A, q.c);
+    if (cell > 0) {
+      g = cubic_of<KIND>(p, n, A, q.c);
+      g0 = g.at(s);
+    }
     if (dir > 0) {
-      const double r = first_zero_up(g, s);
+      const double r = first_zero_up(g, s, g0, tol);
       if (r >= 0.0) return (double)n + r;
       n += 1;  // g > 0 across the rest of the cell: on to the next one
       s = 0.0;
+      p[0] = p[1];
+      p[1] = p[2];
+      p[2] = p[3];
+      p[3] = q.strength * node_f64<KIND>(j, n + 2, id, q.k0, q.k1, q.period);
     } else {
-      const double r = first_zero_down(g, s);
+      const double r = first_zero_down(g, s, g0, tol);
       if (r <= 1.0) return (double)n + r;
       n -= 1;
       s = 1.0;
+      p[3] = p[2];
+      p[2] = p[1];
+      p[1] = p[0];
+      p[0] = q.strength * node_f64<KIND>(j, n - 1, id, q.k0, q.k1, q.period);
     }
   }
   return (double)n + s;  // a long move is continued in the next sweep
@@ -180,8 +220,9 @@ __device__ double relax_site(int32_t n, double s, Cubic g, double A, uint32_t j,
 template <int KIND>
 __device__ double force_at(double ul, double u, double ur, uint32_t j, uint32_t id, double f, const CritParams& q) {
   const double nf = floor(u);
-  const Cubic g = local_force<KIND>(j, (int32_t)nf, id, q.k0, q.k1, q.period, q.strength,
-                                    q.c * (ul + ur) + f, q.c);
+  double p[4];
+  node_window<KIND>(j, (int32_t)nf, id, q, p);
+  const Cubic g = cubic_of<KIND>(p, (int32_t)nf, q.c * (ul + ur) + f, q.c);
   return g.at(u - nf);
 }
 
@@ -227,6 +268,12 @@ __global__ void __launch_bounds__(kCritBlock)
 
   int64_t sweeps = 0;
   int status = 0;
+  // A site whose force is within tol_force / 4 of zero is left where it is,
+  // and a move stops once the force left at the site is within tol_force / 64:
+  // a converged line (every |force| <= tol_force) is reached without chasing
+  // zeros to the last ulp.
+  const double skip = 0.25 * q.tol_force;
+  const double stop = q.tol_force * (1.0 / 64.0);
   // One sweep at drive f: the even sites, then the odd ones (the last site
   // alone when L is odd, since it neighbours site 0).  dir = +1: forward
   // moves; 0: towards the force.
@@ -241,12 +288,14 @@ __global__ void __launch_bounds__(kCritBlock)
         const double A = q.c * (ul + ur) + f;
         const double x = u[j];
         const double nf = floor(x);
-        const Cubic g = local_force<KIND>((uint32_t)j, (int32_t)nf, id, q.k0, q.k1, q.period, q.strength, A, q.c);
+        double p[4];
+        node_window<KIND>((uint32_t)j, (int32_t)nf, id, q, p);
+        const Cubic g = cubic_of<KIND>(p, (int32_t)nf, A, q.c);
         const double g0 = g.at(x - nf);
         int d = dir;
         if (d == 0) d = g0 > 0.0 ? 1 : (g0 < 0.0 ? -1 : 0);
-        if ((d > 0 && g0 > 0.0) || (d < 0 && g0 < 0.0))
-          u[j] = relax_site<KIND>((int32_t)nf, x - nf, g, A, (uint32_t)j, id, q, d);
+        if ((d > 0 && g0 > skip) || (d < 0 && g0 < -skip))
+          u[j] = relax_site<KIND>((int32_t)nf, x - nf, g0, g, p, A, (uint32_t)j, id, q, d, stop);
       }
       __syncthreads();
     }
