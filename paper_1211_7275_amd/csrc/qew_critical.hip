@@ -35,7 +35,12 @@ namespace qew {
 
 namespace {
 
-constexpr int kCritBlock = 256;
+// Threads of a workgroup: one per pair of sites, at most this many (the
+// random-bond kind's FP64 Box-Muller needs more registers than 1024 threads
+// leave without spilling).
+constexpr int kCritMaxBlock = 1024;
+template <int KIND>
+constexpr int crit_max_block() { return KIND == kRF ? 1024 : 512; }
 constexpr int kMaxCells = 64;        // cells one move may cross (then it stops at the cell edge)
 constexpr int kBisect = 64;          // bound on the bracketed Newton steps of one zero
 constexpr int kCheckEvery = 4;       // sweeps between convergence checks
@@ -242,7 +247,7 @@ __device__ void block_maxmin(double& a, double& b, double* red) {
   __syncthreads();
   a = red[0];
   b = red[1];
-  for (int i = 1; i < kCritBlock / 64; ++i) {
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
     a = fmax(a, red[2 * i]);
     b = fmin(b, red[2 * i + 1]);
   }
@@ -250,10 +255,12 @@ __device__ void block_maxmin(double& a, double& b, double* red) {
 
 }  // namespace
 
-// One workgroup per sample.  LDS: u[L] (the trial), v[L] (the last pinned
-// configuration, the trial's start), reduction scratch.
+// One workgroup per sample, one thread per pair of neighbouring sites (2t,
+// 2t + 1), so every lane moves a site in both halves of a sweep.  LDS: u[L]
+// (the trial), v[L] (the last pinned configuration, the trial's start),
+// reduction scratch.
 template <int KIND>
-__global__ void __launch_bounds__(kCritBlock)
+__global__ void __launch_bounds__(crit_max_block<KIND>())
     k_critical(CritParams q, const uint32_t* __restrict__ did, double* __restrict__ u_io,
                double* __restrict__ f_out, int64_t* __restrict__ st_out) {
   extern __shared__ double sh[];
@@ -262,8 +269,9 @@ __global__ void __launch_bounds__(kCritBlock)
   double* v = sh + L;
   double* red = sh + 2 * L;
   const int s = blockIdx.x;
+  const int nt = blockDim.x;
   const uint32_t id = did[s];
-  for (int j = threadIdx.x; j < L; j += kCritBlock) u[j] = u_io[(int64_t)s * L + j];
+  for (int j = threadIdx.x; j < L; j += nt) u[j] = u_io[(int64_t)s * L + j];
   __syncthreads();
 
   int64_t sweeps = 0;
@@ -278,11 +286,12 @@ __global__ void __launch_bounds__(kCritBlock)
   // alone when L is odd, since it neighbours site 0).  dir = +1: forward
   // moves; 0: towards the force.
   auto sweep = [&](double f, int dir) {
+    const int npairs = L >> 1;  // sites 2t and 2t + 1 for t < npairs; an odd L's last site comes third
     const int phases = (L & 1) ? 3 : 2;
     for (int ph = 0; ph < phases; ++ph) {
-      for (int j = threadIdx.x; j < L; j += kCritBlock) {
-        const bool mine = (ph == 2) ? (j == L - 1) : ((j & 1) == ph && !((L & 1) && j == L - 1));
-        if (!mine) continue;
+      const int count = (ph < 2) ? npairs : 1;
+      for (int t = threadIdx.x; t < count; t += nt) {
+        const int j = (ph < 2) ? 2 * t + ph : L - 1;
         const double ul = u[j == 0 ? L - 1 : j - 1];
         const double ur = u[j == L - 1 ? 0 : j + 1];
         const double A = q.c * (ul + ur) + f;
@@ -304,7 +313,7 @@ __global__ void __launch_bounds__(kCritBlock)
   auto check = [&](double f, double& fmax, double& adv) {
     fmax = 0.0;
     adv = INFINITY;
-    for (int j = threadIdx.x; j < L; j += kCritBlock) {
+    for (int j = threadIdx.x; j < L; j += nt) {
       const double F = force_at<KIND>(u[j == 0 ? L - 1 : j - 1], u[j], u[j == L - 1 ? 0 : j + 1], (uint32_t)j,
                                       id, f, q);
       fmax = fmax > fabs(F) ? fmax : fabs(F);
@@ -327,23 +336,23 @@ __global__ void __launch_bounds__(kCritBlock)
   };
 
   double f_lo = q.f_lo, f_hi = q.f_hi;
-  for (int j = threadIdx.x; j < L; j += kCritBlock) v[j] = -INFINITY;  // no advance test at the lower drive
+  for (int j = threadIdx.x; j < L; j += nt) v[j] = -INFINITY;  // no advance test at the lower drive
   __syncthreads();
   int r = relax(f_lo, 0);
   if (r != 0) {
     status = 1;  // no pinned configuration reached at the lower drive
   } else {
-    for (int j = threadIdx.x; j < L; j += kCritBlock) v[j] = u[j];
+    for (int j = threadIdx.x; j < L; j += nt) v[j] = u[j];
     __syncthreads();
     for (int round = 0; round < q.max_rounds && f_hi - f_lo >= q.tol_f; ++round) {
       const double f_mid = 0.5 * (f_lo + f_hi);
       r = relax(f_mid, 1);
       if (r == 0) {
         f_lo = f_mid;
-        for (int j = threadIdx.x; j < L; j += kCritBlock) v[j] = u[j];
+        for (int j = threadIdx.x; j < L; j += nt) v[j] = u[j];
       } else if (r == 1) {
         f_hi = f_mid;
-        for (int j = threadIdx.x; j < L; j += kCritBlock) u[j] = v[j];
+        for (int j = threadIdx.x; j < L; j += nt) u[j] = v[j];
       } else {
         status = 2;  // a trial undecided within max_sweeps
         break;
@@ -353,7 +362,7 @@ __global__ void __launch_bounds__(kCritBlock)
     if (status == 0 && f_hi - f_lo >= q.tol_f) status = 3;  // out of rounds
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < L; j += kCritBlock) u_io[(int64_t)s * L + j] = (status == 0) ? v[j] : u[j];
+  for (int j = threadIdx.x; j < L; j += nt) u_io[(int64_t)s * L + j] = (status == 0) ? v[j] : u[j];
   if (threadIdx.x == 0) {
     f_out[2 * s] = f_lo;
     f_out[2 * s + 1] = f_hi;
@@ -362,7 +371,14 @@ __global__ void __launch_bounds__(kCritBlock)
   }
 }
 
-size_t critical_lds_bytes(int L) { return (size_t)(2 * L + 2 * (kCritBlock / 64)) * sizeof(double); }
+size_t critical_lds_bytes(int L) { return (size_t)(2 * L + 2 * (kCritMaxBlock / 64)) * sizeof(double); }
+
+// Threads per workgroup: one per pair of sites, whole waves, at most `cap`.
+static int critical_block(int L, int cap) {
+  const int pairs = L >> 1;
+  const int t = ((pairs + 63) / 64) * 64;
+  return t < 64 ? 64 : (t > cap ? cap : t);
+}
 
 hipError_t launch_critical(int kind, const CritParams& q, int n_samples, const uint32_t* did, double* u_io,
                            double* f_out, int64_t* st_out, hipStream_t st) {
@@ -372,9 +388,9 @@ hipError_t launch_critical(int kind, const CritParams& q, int n_samples, const u
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (kind == kRF)
-    hipLaunchKernelGGL(k_critical<kRF>, dim3(n_samples), dim3(kCritBlock), lds, st, q, did, u_io, f_out, st_out);
+    hipLaunchKernelGGL(k_critical<kRF>, dim3(n_samples), dim3(critical_block(q.L, crit_max_block<kRF>())), lds, st, q, did, u_io, f_out, st_out);
   else
-    hipLaunchKernelGGL(k_critical<kRB>, dim3(n_samples), dim3(kCritBlock), lds, st, q, did, u_io, f_out, st_out);
+    hipLaunchKernelGGL(k_critical<kRB>, dim3(n_samples), dim3(critical_block(q.L, crit_max_block<kRB>())), lds, st, q, did, u_io, f_out, st_out);
   return hipGetLastError();
 }
 

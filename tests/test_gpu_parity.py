@@ -850,6 +850,28 @@ def test_critical_forces_match_oracle(qew, oracle, kind, L, dids):
         assert np.max(np.abs(F)) <= 1e-9
 
 
+def test_critical_force_paper_shape(qew, oracle):
+    """At the shape of the paper's critical configurations (L = 2048,
+    M = 13777, Sec. III A), where the oracle's Euler bisection is out of
+    reach: the returned configuration is pinned at f_lo (every force of it,
+    evaluated by the oracle, within the tolerance), the bracket is closed to
+    tol_f, and the finer bracket lies inside the coarser one (every trial
+    drive decided alike)."""
+    from paper_1211_7275_amd import critical
+    L, M, dids = 2048, 13777, [0, 1]
+    say("critical forces at L = 2048, M = 13777 (RB), two tolerances")
+    coarse = critical.critical_forces(1, L, M, dids, SEED + 71, f_hi=4.0, tol_f=1e-2, max_sweeps=800_000)
+    fine = critical.critical_forces(1, L, M, dids, SEED + 71, f_hi=4.0, tol_f=1e-3, max_sweeps=800_000)
+    for s, d in enumerate(dids):
+        say("  sample", d, "coarse", coarse["f_lo"][s], coarse["f_hi"][s], "fine", fine["f_lo"][s],
+            fine["f_hi"][s], "sweeps", fine["sweeps"][s])
+        assert fine["f_hi"][s] - fine["f_lo"][s] < 1e-3
+        assert coarse["f_lo"][s] <= fine["f_lo"][s] and fine["f_hi"][s] <= coarse["f_hi"][s]
+        F = oracle.forces(1, 1.0, SEED + 71, d, 1.0, fine["f_lo"][s], fine["u_c"][s], period=M)
+        say("    max |force| of u_c at f_lo:", float(np.max(np.abs(F))))
+        assert np.max(np.abs(F)) <= 1e-9
+
+
 def test_critical_force_statuses(qew):
     """No disorder: pinned only at f = 0 exactly, so the bracket closes on 0
     and the flat line is returned; an impossible sweep budget reports an
