@@ -200,10 +200,11 @@ qew_status qew_run(qew_plan_t *plan, void *d_ws, size_t ws_bytes, void *stream, 
                    double *h_v, double *h_w2, double *h_ubar);
 
 /*
- * qew_run for callers that cannot allocate memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid allocation): the same
- * arguments, kernels and results as qew_run, but the call allocates nothing,
- * on the device or the host.  The chains stay in d_ws (its size and
+ * qew_run for callers that cannot allocate memory (tight serving loops,
+ * harnesses that forbid allocation): the same arguments, kernels and results
+ * as qew_run, but the call allocates nothing, on the device or the host.  Like
+ * qew_run it synchronizes its stream (the tables go in and the series come out
+ * by copies), so the call itself cannot be recorded into a HIP graph.  The chains stay in d_ws (its size and
  * alignment as for qew_run); the plan's tables, tile lists, measurement
  * partials and series live in a device scratch array of the library, 8 MiB
  * per GPU, held from the library's load until the process ends (its address
