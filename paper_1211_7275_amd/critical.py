@@ -145,7 +145,7 @@ def main(argv=None):
     ap.add_argument("--method", choices=("no-passing", "euler"), default="no-passing")
     a = ap.parse_args(argv)
     solve = critical_forces if a.method == "no-passing" else critical_forces_euler
-    solve(a.kind, a.L, a.M, np.arange(1), a.seed, f_hi=a.f_hi, tol_f=1e-2)  # warm-up (library load, kernels)
+    solve(a.kind, min(a.L, 64), min(a.M, 64), np.arange(1), a.seed, f_hi=a.f_hi, tol_f=1e-2)  # warm-up: library and kernels
     t0 = time.perf_counter()
     r = solve(a.kind, a.L, a.M, np.arange(a.samples), a.seed, f_hi=a.f_hi, tol_f=a.tol_f)
     torch.cuda.synchronize()
