@@ -8,8 +8,9 @@
 // of length N = L/2 on z_k = u_2k + i u_2k+1 (after subtracting the sample's
 // first site, which only moves mode 0), followed by the usual split of the
 // even and odd halves.  The complex transform is a Stockham auto-sort FFT in
-// passes of radix 8 (then 4 or 2): every pass reads and writes the batch once,
-// coalesced, with twiddles from sincospi in FP64.  The per-mode values are then
+// passes of radix 8, 64 and 8, 4 or 2: every pass reads and writes the batch
+// once, coalesced, with twiddles from sincospi in FP64; the first pass packs z
+// from the chain as it reads it.  The per-mode values are then
 // averaged over the samples and over caller-given ranges of n (cut into
 // chunks of modes), in a fixed order (no atomics), so repeated runs give
 // identical bits.
@@ -71,39 +72,48 @@ __device__ __forceinline__ void dft<8>(double2* v) {
 // All transform lengths are powers of two, so every index split below is a
 // shift or a mask.  blockIdx.y walks the samples (grid-stride for large S).
 
-// z[s][k] = (u_2k - K) + i (u_2k+1 - K), K = u_0 of sample s.
-__global__ void __launch_bounds__(kBlock)
-    k_sq_pack_plain(const int64_t* __restrict__ off, const double* __restrict__ u, double2* __restrict__ z,
-                    int N, int S) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= N) return;
-  for (int s = blockIdx.y; s < S; s += gridDim.y) {
-    const double* us = u + off[s];
-    const double K = us[0];
-    z[(int64_t)s * N + k] = make_double2(us[2 * k] - K, us[2 * k + 1] - K);
-  }
+// Points of the complex transform: from the previous pass's buffer, or (the
+// first pass) packed on the fly from the chain, z_m = (u_2m - K) + i (u_2m+1 - K)
+// with K = u_0 of the sample.
+enum { kSrcBuffer = 0, kSrcPlain = 1, kSrcSplit = 2 };
+struct FftSource {
+  const double2* buf;      // kSrcBuffer: [S][N]
+  const int64_t* off;      // chains: sample offsets
+  const double* u;         // kSrcPlain
+  const int32_t* cell;     // kSrcSplit
+  const float* frac;
+};
+
+template <int SRC>
+__device__ __forceinline__ double sample_shift(const FftSource& src, int s) {
+  if constexpr (SRC == kSrcPlain) return src.u[src.off[s]];
+  else if constexpr (SRC == kSrcSplit) return (double)src.cell[src.off[s]] + (double)src.frac[src.off[s]];
+  else return 0.0;
 }
 
-__global__ void __launch_bounds__(kBlock)
-    k_sq_pack_split(const int64_t* __restrict__ off, const int32_t* __restrict__ cell,
-                    const float* __restrict__ frac, double2* __restrict__ z, int N, int S) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= N) return;
-  for (int s = blockIdx.y; s < S; s += gridDim.y) {
-    const int64_t b = off[s];
-    const double K = (double)cell[b] + (double)frac[b];
-    const double a0 = (double)cell[b + 2 * k] + (double)frac[b + 2 * k];
-    const double a1 = (double)cell[b + 2 * k + 1] + (double)frac[b + 2 * k + 1];
-    z[(int64_t)s * N + k] = make_double2(a0 - K, a1 - K);
+template <int SRC>
+__device__ __forceinline__ double2 load_point(const FftSource& src, int s, int lgN, int m, double K) {
+  if constexpr (SRC == kSrcBuffer) {
+    return src.buf[((int64_t)s << lgN) + m];
+  } else if constexpr (SRC == kSrcPlain) {
+    const double2 x = *reinterpret_cast<const double2*>(src.u + src.off[s] + 2 * (int64_t)m);
+    return make_double2(x.x - K, x.y - K);
+  } else {
+    const int64_t b = src.off[s] + 2 * (int64_t)m;
+    const int2 c = *reinterpret_cast<const int2*>(src.cell + b);
+    const float2 r = *reinterpret_cast<const float2*>(src.frac + b);
+    return make_double2(((double)c.x + (double)r.x) - K, ((double)c.y + (double)r.y) - K);
   }
 }
 
 // One Stockham pass of radix R = 2^lgR over every transform of the batch:
 // sub-transforms of Ns = 2^lgNs points are done, this pass makes them Ns * R.
 // The twiddles exp(-2 pi i r k / (Ns R)) are powers of the r = 1 twiddle.
-template <int R>
+// The first pass of a transform (SRC = kSrcPlain or kSrcSplit) reads the
+// chain itself; a wave then reads 64 consecutive points per load.
+template <int R, int SRC>
 __global__ void __launch_bounds__(kBlock)
-    k_fft_pass(const double2* __restrict__ in, double2* __restrict__ out, int lgN, int lgNs, int S) {
+    k_fft_pass(FftSource src, double2* __restrict__ out, int lgN, int lgNs, int S) {
   constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
   const int NR = 1 << (lgN - lgR);
   const int j = blockIdx.x * kBlock + threadIdx.x;
@@ -117,11 +127,11 @@ __global__ void __launch_bounds__(kBlock)
     w1 = make_double2(cs, sn);
   }
   for (int s = blockIdx.y; s < S; s += gridDim.y) {
-    const double2* a = in + ((int64_t)s << lgN);
+    const double K = sample_shift<SRC>(src, s);
     double2* o = out + ((int64_t)s << lgN);
     double2 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = a[j + r * NR];
+    for (int r = 0; r < R; ++r) v[r] = load_point<SRC>(src, s, lgN, j + r * NR, K);
     if (lgNs > 0) {
       double2 w = w1;
 #pragma unroll
@@ -133,6 +143,78 @@ __global__ void __launch_bounds__(kBlock)
     dft<R>(v);
 #pragma unroll
     for (int q = 0; q < R; ++q) o[base + (q << lgNs)] = v[q];
+  }
+}
+
+// One Stockham pass of radix 64 = 8 x 8 over every transform of the batch,
+// the same indexing as k_fft_pass with R = 64, so it reads and writes the
+// batch once where three radix-8 passes would do it three times.  A wave
+// covers 8 consecutive j (jj = lane & 7) with 8 threads each (t = lane >> 3):
+// thread t loads the points r = t + 8 r2 (r2 = 0..7), twiddles them, and
+// transforms over r2; after the inner twiddle exp(-2 pi i t q2 / 64) the
+// wave exchanges the 8 x 8 block of each j through LDS, thread t takes q2 = t
+// and transforms over r1, giving the outputs q = t + 8 q1.  Every load and
+// store instruction of a wave moves 8 runs of 8 consecutive points (128 B).
+// The exchange stays inside the wave, whose LDS operations complete in order,
+// so no workgroup barrier is needed.
+__global__ void __launch_bounds__(kBlock)
+    k_fft_pass64(const double2* __restrict__ in, double2* __restrict__ out, int lgN, int lgNs, int S) {
+  constexpr int kPad = 9;  // row stride of the exchange block (against bank conflicts)
+  __shared__ double2 xch[kBlock / 64][8][8 * kPad];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jj = lane & 7, t = lane >> 3;
+  const int NR = 1 << (lgN - 6);
+  const int j = (blockIdx.x * (kBlock / 64) + wv) * 8 + jj;
+  const bool active = j < NR;
+  const int k = j & ((1 << lgNs) - 1);
+  // Twiddles (independent of the sample): the pass's exp(-2 pi i r k / (64 Ns))
+  // for r = t + 8 r2 as a b^r2 with a = exp(-2 pi i t k / (64 Ns)) and
+  // b = exp(-2 pi i 8 k / (64 Ns)), and the inner exp(-2 pi i t q2 / 64) as c^q2.
+  double2 tw[8], iw[8];
+  {
+    double sn, cs;
+    sincospi(-2.0 * (double)(t * (int64_t)k) / (double)(64 << lgNs), &sn, &cs);
+    const double2 a = make_double2(cs, sn);
+    sincospi(-2.0 * (double)(8 * (int64_t)k) / (double)(64 << lgNs), &sn, &cs);
+    const double2 b = make_double2(cs, sn);
+    sincospi(-2.0 * (double)t / 64.0, &sn, &cs);
+    const double2 c = make_double2(cs, sn);
+    tw[0] = a;
+    iw[0] = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int i = 1; i < 8; ++i) {
+      tw[i] = cmul(tw[i - 1], b);
+      iw[i] = cmul(iw[i - 1], c);
+    }
+  }
+  const int base = ((j >> lgNs) << (lgNs + 6)) + k;
+  double2* row = &xch[wv][jj][0];
+  for (int s = blockIdx.y; s < S; s += gridDim.y) {
+    const double2* a = in + ((int64_t)s << lgN);
+    double2* o = out + ((int64_t)s << lgN);
+    double2 v[8];
+#pragma unroll
+    for (int r2 = 0; r2 < 8; ++r2) v[r2] = active ? a[j + (t + 8 * r2) * NR] : make_double2(0.0, 0.0);
+    if (lgNs > 0) {
+#pragma unroll
+      for (int r2 = 0; r2 < 8; ++r2) v[r2] = cmul(v[r2], tw[r2]);
+    }
+    dft<8>(v);  // over r2: v[q2]
+#pragma unroll
+    for (int q2 = 1; q2 < 8; ++q2) v[q2] = cmul(v[q2], iw[q2]);
+#pragma unroll
+    for (int q2 = 0; q2 < 8; ++q2) row[t * kPad + q2] = v[q2];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r1 = 0; r1 < 8; ++r1) v[r1] = row[r1 * kPad + t];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    dft<8>(v);  // over r1: v[q1] = output t + 8 q1
+    if (active) {
+#pragma unroll
+      for (int q1 = 0; q1 < 8; ++q1) o[base + ((t + 8 * q1) << lgNs)] = v[q1];
+    }
   }
 }
 
@@ -212,25 +294,41 @@ hipError_t launch_sq(const int64_t* off, int S, int64_t L, const double* u_plain
   const int N = (int)(L / 2);
   int lgN = 0;
   while ((1 << lgN) < N) ++lgN;
-  if (u_plain)
-    hipLaunchKernelGGL(k_sq_pack_plain, grid2(N, S), dim3(kBlock), 0, st, off, u_plain, bufA, N, S);
-  else
-    hipLaunchKernelGGL(k_sq_pack_split, grid2(N, S), dim3(kBlock), 0, st, off, split.cell, split.frac,
-                       bufA, N, S);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   double2* in = bufA;
   double2* outb = bufB;
-  for (int lgNs = 0; lgNs < lgN;) {
+  // The first pass (radix 8, or 4 or 2 for the shortest transforms) packs the
+  // chain as it reads it; radix-64 passes follow while 64 or more points per
+  // sub-transform remain to be combined, then radix 8, 4 or 2.
+  const FftSource chain{nullptr, off, u_plain, split.cell, split.frac};
+  const int lg0 = lgN >= 3 ? 3 : lgN;
+  {
+    const dim3 g = grid2(N >> lg0, S);
+    if (u_plain) {
+      if (lg0 == 3) hipLaunchKernelGGL((k_fft_pass<8, kSrcPlain>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+      else if (lg0 == 2) hipLaunchKernelGGL((k_fft_pass<4, kSrcPlain>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+      else hipLaunchKernelGGL((k_fft_pass<2, kSrcPlain>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+    } else {
+      if (lg0 == 3) hipLaunchKernelGGL((k_fft_pass<8, kSrcSplit>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+      else if (lg0 == 2) hipLaunchKernelGGL((k_fft_pass<4, kSrcSplit>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+      else hipLaunchKernelGGL((k_fft_pass<2, kSrcSplit>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  int lgNs = lg0;
+  while (lgNs < lgN) {
     const int rem = lgN - lgNs;
-    const int lgR = rem >= 3 ? 3 : rem;
+    const int lgR = rem >= 6 ? 6 : (rem >= 3 ? 3 : rem);
     const dim3 g = grid2(N >> lgR, S);
-    if (lgR == 3)
-      hipLaunchKernelGGL((k_fft_pass<8>), g, dim3(kBlock), 0, st, in, outb, lgN, lgNs, S);
+    const FftSource buf{in, nullptr, nullptr, nullptr, nullptr};
+    if (lgR == 6)
+      hipLaunchKernelGGL(k_fft_pass64, grid2((int64_t)(N >> 6) * 8, S), dim3(kBlock), 0, st, in, outb, lgN, lgNs, S);
+    else if (lgR == 3)
+      hipLaunchKernelGGL((k_fft_pass<8, kSrcBuffer>), g, dim3(kBlock), 0, st, buf, outb, lgN, lgNs, S);
     else if (lgR == 2)
-      hipLaunchKernelGGL((k_fft_pass<4>), g, dim3(kBlock), 0, st, in, outb, lgN, lgNs, S);
+      hipLaunchKernelGGL((k_fft_pass<4, kSrcBuffer>), g, dim3(kBlock), 0, st, buf, outb, lgN, lgNs, S);
     else
-      hipLaunchKernelGGL((k_fft_pass<2>), g, dim3(kBlock), 0, st, in, outb, lgN, lgNs, S);
+      hipLaunchKernelGGL((k_fft_pass<2, kSrcBuffer>), g, dim3(kBlock), 0, st, buf, outb, lgN, lgNs, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     lgNs += lgR;
     double2* t = in;
