@@ -104,7 +104,7 @@ hipError_t launch_critical(int kind, const CritParams& q, int n_samples, const u
 
 // Structure factor at one measurement: pack, FFT passes, per-mode |U_n/L|^2,
 // binned mean over samples into out[n_bins].  Every L_s equals L (power of
-// two); u_plain != nullptr selects the FP64 state, else `split`.
+// two, at least 8); u_plain != nullptr selects the FP64 state, else `split`.
 // The bins are cut into n_chunks chunks of modes [chunk_lo[c], chunk_lo[c+1])
 // (bin b owns chunks chunk_first[b] .. chunk_first[b+1]-1); `part` holds one
 // partial sum per chunk.

@@ -297,21 +297,19 @@ hipError_t launch_sq(const int64_t* off, int S, int64_t L, const double* u_plain
   hipError_t e = hipSuccess;
   double2* in = bufA;
   double2* outb = bufB;
-  // The first pass (radix 8, or 4 or 2 for the shortest transforms) packs the
+  // The first pass (radix 8, or 4 for L = 8: the plan admits L >= 8) packs the
   // chain as it reads it; radix-64 passes follow while 64 or more points per
   // sub-transform remain to be combined, then radix 8, 4 or 2.
   const FftSource chain{nullptr, off, u_plain, split.cell, split.frac};
-  const int lg0 = lgN >= 3 ? 3 : lgN;
+  const int lg0 = lgN >= 3 ? 3 : 2;
   {
     const dim3 g = grid2(N >> lg0, S);
     if (u_plain) {
       if (lg0 == 3) hipLaunchKernelGGL((k_fft_pass<8, kSrcPlain>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
-      else if (lg0 == 2) hipLaunchKernelGGL((k_fft_pass<4, kSrcPlain>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
-      else hipLaunchKernelGGL((k_fft_pass<2, kSrcPlain>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+      else hipLaunchKernelGGL((k_fft_pass<4, kSrcPlain>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
     } else {
       if (lg0 == 3) hipLaunchKernelGGL((k_fft_pass<8, kSrcSplit>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
-      else if (lg0 == 2) hipLaunchKernelGGL((k_fft_pass<4, kSrcSplit>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
-      else hipLaunchKernelGGL((k_fft_pass<2, kSrcSplit>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
+      else hipLaunchKernelGGL((k_fft_pass<4, kSrcSplit>), g, dim3(kBlock), 0, st, chain, in, lgN, 0, S);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

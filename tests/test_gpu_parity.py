@@ -802,6 +802,27 @@ def test_structure_factor_full_size(qew, oracle, L, samples):
         assert rel.max() <= 1e-9
 
 
+@pytest.mark.parametrize("L", [8, 16, 32, 64, 128, 512, 2048, 8192])
+def test_structure_factor_short_lengths(qew, oracle, L):
+    """Every mode of seeded rough lines (three samples) at the lengths whose
+    transforms mix the first pass (radix 4 or 8, packing the chain) with
+    radix-64 passes and radix 8, 4 or 2 tails, both precisions, against the
+    oracle's FFT."""
+    rng = np.random.default_rng(1000 + L)
+    states = []
+    for _ in range(3):
+        u = np.cumsum(rng.normal(size=L)) * 0.3 + 7.0
+        states.append(np.floor(u) + (u - np.floor(u)).astype(np.float32))
+    edges = workloads.sq_edges_full(L)
+    want = np.mean([oracle.sq_binned(oracle.structure_factor(u), edges) for u in states], axis=0)
+    p = workloads.custom(0, [L] * 3, 1.0, 0, [0], SEED, sq_edges=edges)
+    for prec in (qew.QEW_FP64_PLAIN, qew.QEW_FP32_SPLIT):
+        got, _ = _sq_gpu(qew, p, prec, qew.QEW_ONE_STEP, states=states, step=0)
+        err = np.abs(got[0] - want)
+        say("S_q L", L, "precision", prec, "max rel err", float(np.max(err / want)))
+        assert np.all(err <= 1e-9 * want + 1e-13 * want.max())
+
+
 # ------------------------------------------------------ STD f-scan (Sec. IV)
 
 def test_fscan_gpu_matches_oracle(qew, oracle):
