@@ -55,6 +55,16 @@ struct Cubic {
 
 constexpr double kEps = 2.220446049250313e-16;
 
+// a / b (b != 0) to about an ulp: the hardware reciprocal refined by one
+// Newton step.  The quotients below steer bracketed searches and place
+// turning points, where an ulp more or less changes nothing, and the full
+// IEEE division sequence is a long dependent chain on the critical path.
+__device__ __forceinline__ double quot(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  return a * r;
+}
+
 // A point next to the zero of g on [lo, hi], where g is monotone with
 // g(lo) = glo > 0 >= g(hi) = ghi (up) or glo >= 0 > ghi (down).  The answer
 // lies on the near side of the zero -- g > 0 (up) or g < 0 (down) -- so a move
@@ -75,7 +85,7 @@ __device__ double bracketed_zero(const Cubic& g, double lo, double hi, double gl
     const double e = from_lo ? lo : hi;
     const double ge = from_lo ? glo : ghi;
     const double d = g.slope(e);
-    double x = (d != 0.0) ? e - ge / d : 0.5 * (lo + hi);
+    double x = (d != 0.0) ? e - quot(ge, d) : 0.5 * (lo + hi);
     if (from_lo != up && fabs(ge) <= tol) {
       const double off = fmax(fabs(e - x), 4.0 * kEps);
       x = up ? x - off : x + off;
@@ -129,15 +139,15 @@ __device__ int turning_points(const Cubic& g, double lo, double hi, double t[2])
   double r[2];
   int n = 0;
   if (a == 0.0) {
-    if (b != 0.0) r[n++] = -c / b;
+    if (b != 0.0) r[n++] = quot(-c, b);
   } else {
     const double disc = b * b - 4.0 * a * c;
     if (disc > 0.0) {
       const double q = -0.5 * (b + copysign(sqrt(disc), b));
-      r[n++] = q / a;
-      if (q != 0.0) r[n++] = c / q;
+      r[n++] = quot(q, a);
+      if (q != 0.0) r[n++] = quot(c, q);
     } else if (disc == 0.0) {
-      r[n++] = -b / (2.0 * a);
+      r[n++] = quot(-b, 2.0 * a);
     }
   }
   if (n == 2 && r[1] < r[0]) {
