@@ -35,12 +35,8 @@ namespace qew {
 
 namespace {
 
-// Threads of a workgroup: one per pair of sites, at most this many (the
-// random-bond kind's FP64 Box-Muller needs more registers than 1024 threads
-// leave without spilling).
+// Threads of a workgroup: one per pair of sites, at most this many.
 constexpr int kCritMaxBlock = 1024;
-template <int KIND>
-constexpr int crit_max_block() { return KIND == kRF ? 1024 : 512; }
 constexpr int kMaxCells = 64;        // cells one move may cross (then it stops at the cell edge)
 constexpr int kBisect = 64;          // bound on the bracketed Newton steps of one zero
 constexpr int kCheckEvery = 4;       // sweeps between convergence checks
@@ -103,11 +99,20 @@ __device__ double bracketed_zero(const Cubic& g, double lo, double hi, double gl
   return up ? lo : hi;
 }
 
-// The strength-scaled nodes n-1 .. n+2 of site j: the Catmull-Rom window of cell n.
+// The strength-scaled nodes n-1 .. n+2 of site j: the Catmull-Rom window of
+// cell n.  The random-bond kind makes them one at a time: four FP64
+// Box-Muller transforms at once would hold more registers than 1024 threads
+// per workgroup leave (measured: the sequential form is faster there, the
+// interleaved one for the uniform nodes).
 template <int KIND>
 __device__ void node_window(uint32_t j, int32_t n, uint32_t id, const CritParams& q, double p[4]) {
+  if constexpr (KIND == kRF) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) p[i] = q.strength * node_f64<KIND>(j, n - 1 + i, id, q.k0, q.k1, q.period);
+    for (int i = 0; i < 4; ++i) p[i] = q.strength * node_f64<KIND>(j, n - 1 + i, id, q.k0, q.k1, q.period);
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) p[i] = q.strength * node_f64<KIND>(j, n - 1 + i, id, q.k0, q.k1, q.period);
+  }
 }
 
 // Local force in cell n from its window p.
@@ -270,7 +275,7 @@ __device__ void block_maxmin(double& a, double& b, double* red) {
 // (the trial), v[L] (the last pinned configuration, the trial's start),
 // reduction scratch.
 template <int KIND>
-__global__ void __launch_bounds__(crit_max_block<KIND>())
+__global__ void __launch_bounds__(kCritMaxBlock)
     k_critical(CritParams q, const uint32_t* __restrict__ did, double* __restrict__ u_io,
                double* __restrict__ f_out, int64_t* __restrict__ st_out) {
   extern __shared__ double sh[];
@@ -383,11 +388,11 @@ __global__ void __launch_bounds__(crit_max_block<KIND>())
 
 size_t critical_lds_bytes(int L) { return (size_t)(2 * L + 2 * (kCritMaxBlock / 64)) * sizeof(double); }
 
-// Threads per workgroup: one per pair of sites, whole waves, at most `cap`.
-static int critical_block(int L, int cap) {
+// Threads per workgroup: one per pair of sites, whole waves, at most kCritMaxBlock.
+static int critical_block(int L) {
   const int pairs = L >> 1;
   const int t = ((pairs + 63) / 64) * 64;
-  return t < 64 ? 64 : (t > cap ? cap : t);
+  return t < 64 ? 64 : (t > kCritMaxBlock ? kCritMaxBlock : t);
 }
 
 hipError_t launch_critical(int kind, const CritParams& q, int n_samples, const uint32_t* did, double* u_io,
@@ -398,9 +403,9 @@ hipError_t launch_critical(int kind, const CritParams& q, int n_samples, const u
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (kind == kRF)
-    hipLaunchKernelGGL(k_critical<kRF>, dim3(n_samples), dim3(critical_block(q.L, crit_max_block<kRF>())), lds, st, q, did, u_io, f_out, st_out);
+    hipLaunchKernelGGL(k_critical<kRF>, dim3(n_samples), dim3(critical_block(q.L)), lds, st, q, did, u_io, f_out, st_out);
   else
-    hipLaunchKernelGGL(k_critical<kRB>, dim3(n_samples), dim3(critical_block(q.L, crit_max_block<kRB>())), lds, st, q, did, u_io, f_out, st_out);
+    hipLaunchKernelGGL(k_critical<kRB>, dim3(n_samples), dim3(critical_block(q.L)), lds, st, q, did, u_io, f_out, st_out);
   return hipGetLastError();
 }
 
