@@ -75,10 +75,18 @@ def _elf_sections(data):
     return out
 
 
-def kernel_source_hash():
-    """sha256 (first 16 hex) of the machine code of the fused stepping kernel
-    (every dense k_step_fused instantiation) in the gfx950 code object of the
-    built library: it changes exactly when that kernel's compiled code does."""
+# Kernels whose measured traffic the bench line carries, by symbol pattern:
+# every dense fused instantiation, and the FP64 one-step kernel of the
+# benchmark's disorder (random field) without measurement.
+FUSED_SYMBOLS = rb"k_step_fusedILi\d+ELi\d+ELb0E"
+PLAIN_SYMBOLS = rb"k_step_plainILi0ELb0E"
+
+
+def kernel_source_hash(pattern=FUSED_SYMBOLS):
+    """sha256 (first 16 hex) of the machine code of the kernels whose symbols
+    match `pattern` (default: every dense k_step_fused instantiation) in the
+    gfx950 code object of the built library: it changes exactly when those
+    kernels' compiled code does."""
     import hashlib
     import re
     import struct
@@ -107,8 +115,7 @@ def kernel_source_hash():
         st_name, st_info, st_other, st_shndx, st_value, st_size = struct.unpack_from(
             "<IBBHQQ", code, sym_off + 24 * i)
         name = code[str_off + st_name:code.index(b"\0", str_off + st_name)]
-        # the dense variant (third template argument false) is the kernel the benchmark runs
-        if re.search(rb"k_step_fusedILi\d+ELi\d+ELb0E", name) and st_size > 0 and not name.endswith(b".kd"):
+        if re.search(pattern, name) and st_size > 0 and not name.endswith(b".kd"):
             syms.append((name, st_value, st_size))
     for name, value, size in sorted(syms):
         start = text_off + (value - text_addr)
@@ -117,12 +124,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(k, tile):
-    """HBM bytes per fused launch measured by rocprofv3 (FETCH_SIZE/WRITE_SIZE,
-    copy-calibrated) for this kernel code and geometry, else None."""
+def committed_traffic(k=None, tile=None, plain=False):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE/WRITE_SIZE,
+    copy-calibrated) for this kernel code (and fused geometry), else None."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
-    want = f"k={k} tile={tile} source={kernel_source_hash()}"
+    if plain:
+        want = f"plain source={kernel_source_hash(PLAIN_SYMBOLS)}"
+    else:
+        want = f"fused k={k} tile={tile} source={kernel_source_hash()}"
     for ln in open(TRAFFIC_SUMMARY):
         if ln.startswith("traffic_per_launch ") and want in ln:
             for tok in ln.split():
@@ -207,7 +217,7 @@ def plain_roofline(st, info, steps):
     bytes_per_launch = 16.0 * info.total_sites * steps / max(st.step_launches, 1)
     gbs = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": committed_traffic(plain=True),
             "launch_ms": round(launch_ms, 5), "launches": int(st.step_launches)}
 
 
@@ -491,7 +501,8 @@ def main():
                     help="only run a 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output under DIR and exit")
-    ap.add_argument("--source-hash", action="store_true", help="print the hash of the fused kernel's machine code and exit")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hashes of the fused and the plain kernels' machine code and exit")
     ap.add_argument("--workload", default="c3", choices=sorted(OTHER_WORKLOADS) + ["c3", "plain0", "plain0small"],
                     help="c3 (default): the benchmark line; others print one line for that "
                          "workload's FP32 split fused throughput (--steps sets the horizon)")
@@ -501,7 +512,7 @@ def main():
         print(summarize_profile(args.summarize_profile))
         return
     if args.source_hash:
-        print(kernel_source_hash())
+        print(f"fused source={kernel_source_hash()} plain source={kernel_source_hash(PLAIN_SYMBOLS)}")
         return
 
     if args.gpus != 1:

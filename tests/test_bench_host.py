@@ -72,13 +72,19 @@ def test_summarizer_counters_per_variant(tmp_path):
 
 def test_traffic_lookup_needs_the_measured_kernel_code(monkeypatch, tmp_path):
     summary = tmp_path / "traffic.md"
-    summary.write_text("traffic_per_launch fused k=56 tile=2048 source=00aa bytes=123\n")
+    summary.write_text("traffic_per_launch fused k=56 tile=2048 source=00aa bytes=123\n"
+                       "traffic_per_launch plain source=00cc bytes=45\n")
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "00aa")
+    hashes = {bench.FUSED_SYMBOLS: "00aa", bench.PLAIN_SYMBOLS: "00cc"}
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda pattern=bench.FUSED_SYMBOLS: hashes[pattern])
     assert bench.committed_traffic(56, 2048) == 123
     assert bench.committed_traffic(48, 2048) is None
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "00bb")  # kernel changed since
+    assert bench.committed_traffic(plain=True) == 45
+    hashes[bench.FUSED_SYMBOLS] = "00bb"  # the fused kernel changed since
     assert bench.committed_traffic(56, 2048) is None
+    assert bench.committed_traffic(plain=True) == 45
+    hashes[bench.PLAIN_SYMBOLS] = "00dd"  # and the plain one
+    assert bench.committed_traffic(plain=True) is None
 
 
 def test_benchmark_problem_is_the_whole_workload():
